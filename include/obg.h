@@ -1,0 +1,140 @@
+/*
+ * obg.h -- octree background modelling on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the GPU library libobg.so.  The method is the one of "Background
+ * Modeling Using Octree Color Quantization" (arXiv 1412.1945):
+ *
+ *   1. every pixel colour is a path in an octree: at level i the child index
+ *      is built from bit 7-i of R, G and B (Algorithm 1, Store Color);
+ *   2. a frame's octree, pruned to depth d (Section 2), is exactly the set of
+ *      depth-d paths that occur in the frame; here it is an occupancy bitset;
+ *   3. the trees of T training frames are merged, keeping a path when the
+ *      fraction of trees that contain it reaches a threshold (Algorithm 2,
+ *      Merge Trees, Section 3);
+ *   4. a pixel of an incoming frame is foreground when its path is missing
+ *      from the merged tree (Algorithm 3, Check Color, Section 4);
+ *   5. optionally the frame is split into rectangular regions, each with its
+ *      own trees (Sections 3 and 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Child index at level i (i = 0 just below the root): 4*r + 2*g + b, where r,
+ * g, b are bit 7-i of the 8-bit R, G, B values (the paper prints the index as
+ * a sum of the three bits; a sum cannot address eight children, so the bits
+ * are concatenated, red most significant).
+ * Path key of a depth-d node: its child indices c_0..c_{d-1} as base-8
+ * digits, c_0 most significant; 0 <= key < 8^d.
+ * Bitset of one tree: ceil(8^d / 32) uint32 words; key k is bit (k & 31) of
+ * word (k >> 5).  Bits past 8^d (d = 1) are ignored on input, 0 on output.
+ * Regions: region_w = region_h = 0 means one tree per frame.  Otherwise the
+ * frame is cut into a row-major grid of region_w x region_h rectangles (the
+ * last column/row may be narrower/shorter); region id of pixel (x, y) =
+ * (y / region_h) * ceil(width / region_w) + x / region_w.  Per frame the
+ * bitsets of all regions are stored back to back, region 0 first.
+ * Frames: packed RGB8, pixel x of row y at byte y*row_pitch + 3x (R, G, B);
+ * frame f starts frame_pitch bytes after frame f-1.  The buffer must span
+ * n_frames * frame_pitch bytes.
+ * Masks: per frame height rows of ceil(width / 64) uint64 words; pixel x is
+ * bit (x & 63) of word (x >> 6); 1 = foreground; bits past width are 0.
+ * Frames follow each other without gaps.
+ *
+ * Memory and streams: every buffer pointer is a DEVICE pointer owned by the
+ * caller.  Calls validate their arguments, enqueue kernels on `stream`
+ * (NULL = the default stream) and return without waiting; the library keeps
+ * no pointer after a call returns (except inside an obg_batch, see below).
+ * Outputs are written completely by the call (no pre-zeroing needed).
+ * Faults inside a kernel surface at the caller's next synchronisation.
+ *
+ * Errors: 0 (OBG_OK) or a negative code; obg_last_error() returns a message
+ * for the calling thread's last failed call.  Nothing is enqueued when a call
+ * fails validation.
+ */
+#ifndef OBG_H
+#define OBG_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OBG_OK           0
+#define OBG_EINVAL      -1   /* bad size, depth, threshold, NULL pointer ... */
+#define OBG_EALIGN      -2   /* frame pointer or pitch not 16-byte aligned    */
+#define OBG_EHIP        -3   /* HIP launch / runtime failure                  */
+#define OBG_ENOMEM      -4   /* host or device allocation failed              */
+
+typedef struct obg_geom {
+    int32_t width, height;     /* pixels, >= 1                                */
+    int64_t row_pitch;         /* bytes, >= 3*width, multiple of 16           */
+    int64_t frame_pitch;       /* bytes, >= height*row_pitch, multiple of 16  */
+    int32_t depth;             /* d in [1, 8]: octree levels kept (Section 2) */
+    int32_t region_w, region_h;/* 0,0 = one tree per frame; else >= 1 each    */
+} obg_geom;
+
+/* Number of regions of the geometry (1 without regions); -1 if invalid. */
+int64_t obg_num_regions(const obg_geom *g);
+/* uint32 words of one frame's occupancy: n_regions * ceil(8^d / 32). */
+int64_t obg_occ_words(const obg_geom *g);
+/* uint64 words of one frame's mask: height * ceil(width / 64). */
+int64_t obg_mask_words(const obg_geom *g);
+
+/*
+ * Per-frame pruned octrees (Algorithm 1 for every pixel, pruned to depth d
+ * as in Section 2), as occupancy bitsets.
+ *   rgb    : n_frames frames (layout above), 16-byte aligned.
+ *   occ    : out, [n_frames][n_regions][ceil(8^d/32)] uint32; bit k set iff
+ *            some pixel of that frame and region has path key k.
+ *   counts : out, NULLABLE, [n_frames][n_regions][8^d] uint32; pixels per key
+ *            (node pixel counts of the pruned tree; diagnostic).
+ * n_frames = 0 enqueues nothing.
+ */
+int obg_train_frame(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
+                    uint32_t *occ, uint32_t *counts, hipStream_t stream);
+
+/*
+ * Merge of per-frame trees (Algorithm 2).  A path key k of region r is kept
+ * iff C = number of trees in the window whose bitset has k satisfies
+ * C * thr_den >= thr_num * n_trees (the paper's count/numberOfTrees >=
+ * threshold, done exactly in integers).  Because every tree that holds a
+ * path also holds all its prefixes, this per-key test gives the same depth-d
+ * nodes as the paper's level-by-level recursion.
+ *   occ_ring : [ring_len][n_regions][ceil(8^d/32)] uint32, per-frame bitsets.
+ *   window   : slots first, first+1, ..., first+n_trees-1 (mod ring_len).
+ *   leafset  : out, [n_regions][ceil(8^d/32)] uint32, the merged tree's
+ *              depth-d nodes.
+ * EINVAL: n_trees < 1, n_trees > ring_len, n_trees > 65535, first outside
+ * [0, ring_len), thr_num = 0 (a zero threshold would keep paths no tree
+ * has), thr_den = 0.  thr_num > thr_den is allowed: nothing is kept.
+ * Only depth and regions of g are used.
+ */
+int obg_merge(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len,
+              int32_t first, int32_t n_trees, uint32_t thr_num, uint32_t thr_den,
+              uint32_t *leafset, hipStream_t stream);
+
+/*
+ * Foreground detection (Algorithm 3 for every pixel, Section 4): mask bit 1
+ * iff the pixel's depth-d path key is not in its region's leaf set.
+ *   rgb     : n_frames frames (layout above), 16-byte aligned.
+ *   leafset : [n_regions][ceil(8^d/32)] uint32 (as written by obg_merge).
+ *   mask    : out, [n_frames][height][ceil(width/64)] uint64.
+ *   occ_out : out, NULLABLE; when given, the occupancy of every classified
+ *             frame as obg_train_frame would write it (one pass over the
+ *             pixels produces both; used to keep a ring of recent trees).
+ */
+int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
+                 const uint32_t *leafset, uint64_t *mask, uint32_t *occ_out,
+                 hipStream_t stream);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *obg_last_error(void);
+
+/* Library version string. */
+const char *obg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OBG_H */

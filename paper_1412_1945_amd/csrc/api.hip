@@ -1,0 +1,265 @@
+// api.hip -- C ABI of libobg.so: argument checks, work split, launches.
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/obg.h"
+#include "internal.h"
+
+using namespace obg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(OBG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Validated geometry and the sizes derived from it.
+struct Geo {
+    int32_t width, height, depth, region_w, region_h;
+    int64_t row_pitch, frame_pitch;
+    int32_t reg_cols, reg_rows, n_regions;
+    int32_t words;             // uint32 words per tree
+    int32_t mask_row_words;    // uint64 words per mask row
+};
+
+int check_geom(const obg_geom *g, Geo *o, bool pixels) {
+    if (!g) return fail(OBG_EINVAL, "geometry pointer is NULL");
+    if (g->width < 1 || g->height < 1) return fail(OBG_EINVAL, "width and height must be >= 1 (got %d x %d)", g->width, g->height);
+    if (g->depth < 1 || g->depth > 8) return fail(OBG_EINVAL, "depth must be in [1, 8] (got %d)", g->depth);
+    if (g->region_w < 0 || g->region_h < 0 || ((g->region_w == 0) != (g->region_h == 0)))
+        return fail(OBG_EINVAL, "region_w and region_h must both be 0 or both >= 1 (got %d, %d)", g->region_w, g->region_h);
+    if (g->width > (1 << 24) || g->height > (1 << 24)) return fail(OBG_EINVAL, "frame side above 2^24");
+    o->width = g->width;
+    o->height = g->height;
+    o->depth = g->depth;
+    o->region_w = g->region_w;
+    o->region_h = g->region_h;
+    o->row_pitch = g->row_pitch;
+    o->frame_pitch = g->frame_pitch;
+    o->reg_cols = g->region_w ? (g->width + g->region_w - 1) / g->region_w : 1;
+    o->reg_rows = g->region_h ? (g->height + g->region_h - 1) / g->region_h : 1;
+    if ((int64_t)o->reg_cols * o->reg_rows > (1 << 30)) return fail(OBG_EINVAL, "too many regions");
+    o->n_regions = o->reg_cols * o->reg_rows;
+    o->words = leaf_words(g->depth);
+    o->mask_row_words = (g->width + 63) / 64;
+    if (pixels) {
+        if (g->row_pitch < 3 * (int64_t)g->width)
+            return fail(OBG_EINVAL, "row_pitch %lld < 3*width %lld", (long long)g->row_pitch, 3LL * g->width);
+        if (g->frame_pitch < (int64_t)g->height * g->row_pitch)
+            return fail(OBG_EINVAL, "frame_pitch %lld < height*row_pitch", (long long)g->frame_pitch);
+        if (g->row_pitch % 16 || g->frame_pitch % 16)
+            return fail(OBG_EALIGN, "row_pitch and frame_pitch must be multiples of 16 bytes");
+    }
+    return OBG_OK;
+}
+
+int cu_count() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cache[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+        cache[dev] = n;
+    }
+    return cache[dev];
+}
+
+const size_t kStripLdsMax = 64 * 1024;
+
+// Does the LDS strip kernel handle this geometry and mode?
+bool strip_ok(const Geo &g, int mode) {
+    if (g.depth > 6) return false;
+    if (g.region_w && (g.region_w % 16) != 0) return false;
+    const size_t tiles = (size_t)g.reg_cols * g.words * 4;
+    const size_t lds = tiles * (((mode & MODE_MASK) ? 1 : 0) + ((mode & MODE_OCC) ? 1 : 0));
+    return lds <= kStripLdsMax;
+}
+
+int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, const uint32_t *leaf,
+               uint64_t *mask, uint32_t *occ, uint32_t *counts, hipStream_t st) {
+    hipError_t e;
+    const int64_t occ_words = (int64_t)n_frames * g.n_regions * g.words;
+    if (mode & MODE_OCC) {
+        if ((e = launch_fill_u32(occ, occ_words, 0u, st)) != hipSuccess) return hip_fail(e, "zero occupancy");
+    }
+    if (mode & MODE_COUNTS) {
+        const int64_t n = (int64_t)n_frames * g.n_regions * leaf_count(g.depth);
+        if ((e = launch_fill_u32(counts, n, 0u, st)) != hipSuccess) return hip_fail(e, "zero counts");
+    }
+    if (!strip_ok(g, mode)) {
+        GenericArgs a{};
+        a.rgb = rgb;
+        a.frame_pitch = g.frame_pitch;
+        a.row_pitch = g.row_pitch;
+        a.width = g.width;
+        a.height = g.height;
+        a.n_frames = n_frames;
+        a.depth = g.depth;
+        a.region_w = g.region_w;
+        a.region_h = g.region_h;
+        a.reg_cols = g.reg_cols;
+        a.n_regions = g.n_regions;
+        a.mask_row_words = g.mask_row_words;
+        a.leaf = leaf;
+        a.mask = mask;
+        a.occ = occ;
+        a.counts = counts;
+        if ((e = launch_generic(mode, a, st)) != hipSuccess) return hip_fail(e, "generic kernel launch");
+        return OBG_OK;
+    }
+    StripArgs a{};
+    a.rgb = rgb;
+    a.frame_pitch = g.frame_pitch;
+    a.row_pitch = g.row_pitch;
+    a.width = g.width;
+    a.height = g.height;
+    a.n_frames = n_frames;
+    a.gpr = 4 * g.mask_row_words;
+    a.strip_rows = g.region_h ? g.region_h : g.height;
+    if (a.strip_rows > g.height) a.strip_rows = g.height;
+    a.n_strips = (g.height + a.strip_rows - 1) / a.strip_rows;
+    a.reg_cols = g.reg_cols;
+    a.n_regions = g.n_regions;
+    a.div_gpr = make_fastdiv((uint32_t)a.gpr);
+    a.div_tile = make_fastdiv(g.region_w ? (uint32_t)(g.region_w / 16) : (uint32_t)a.gpr);
+    const int64_t groups_strip = (int64_t)a.strip_rows * a.gpr;
+    if (groups_strip > (1LL << 30)) return fail(OBG_EINVAL, "frame too large");
+    const int block = 256;
+    const size_t lds = (size_t)g.reg_cols * g.words * 4 *
+                       (((mode & MODE_MASK) ? 1 : 0) + ((mode & MODE_OCC) ? 1 : 0));
+    const int cus = cu_count();
+    int per_cu = lds ? (int)((160 * 1024) / lds) : 8;
+    if (per_cu > 8) per_cu = 8;
+    if (per_cu < 1) per_cu = 1;
+    const int64_t n_sf = (int64_t)a.n_strips * n_frames;
+    int64_t spans;
+    int64_t target = (int64_t)cus * per_cu;
+    if (mode & MODE_OCC) {
+        // fewer, larger items: each (frame, strip) segment costs one flush
+        int64_t t2 = (int64_t)cus * (per_cu < 2 ? per_cu : 2);
+        spans = (t2 + n_sf - 1) / n_sf;
+        const int64_t cap = (groups_strip + block - 1) / block;
+        if (spans > cap) spans = cap;
+        if (spans < 1) spans = 1;
+        target = t2;
+    } else {
+        spans = (groups_strip + 2047) / 2048;
+    }
+    const int64_t span = (groups_strip + spans - 1) / spans;
+    const int64_t n_items = n_sf * spans;
+    if (n_items > 0x7FFFFFFF) return fail(OBG_EINVAL, "too many work items (n_frames too large for one call)");
+    a.span = (int32_t)span;
+    a.spans = (int32_t)spans;
+    a.n_items = (int32_t)n_items;
+    a.leaf = leaf;
+    a.mask = mask;
+    a.mask_row_words = g.mask_row_words;
+    a.occ = occ;
+    a.counts = counts;
+    const int grid = (int)(n_items < target ? n_items : target);
+    if ((e = launch_strip(g.depth, mode, a, grid, block, lds, st)) != hipSuccess)
+        return hip_fail(e, "strip kernel launch");
+    return OBG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t obg_num_regions(const obg_geom *g) {
+    Geo o;
+    return check_geom(g, &o, false) == OBG_OK ? o.n_regions : -1;
+}
+
+int64_t obg_occ_words(const obg_geom *g) {
+    Geo o;
+    return check_geom(g, &o, false) == OBG_OK ? (int64_t)o.n_regions * o.words : -1;
+}
+
+int64_t obg_mask_words(const obg_geom *g) {
+    Geo o;
+    return check_geom(g, &o, false) == OBG_OK ? (int64_t)o.height * o.mask_row_words : -1;
+}
+
+int obg_train_frame(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, uint32_t *occ,
+                    uint32_t *counts, hipStream_t stream) {
+    Geo o;
+    int rc = check_geom(g, &o, true);
+    if (rc) return rc;
+    if (n_frames < 0) return fail(OBG_EINVAL, "n_frames < 0");
+    if (n_frames == 0) return OBG_OK;
+    if (!rgb || !occ) return fail(OBG_EINVAL, "rgb and occ must not be NULL");
+    if ((uintptr_t)rgb % 16) return fail(OBG_EALIGN, "rgb must be 16-byte aligned");
+    const int mode = MODE_OCC | (counts ? MODE_COUNTS : 0);
+    return run_pixels(o, mode, rgb, n_frames, nullptr, nullptr, occ, counts, stream);
+}
+
+int obg_merge(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len, int32_t first,
+              int32_t n_trees, uint32_t thr_num, uint32_t thr_den, uint32_t *leafset,
+              hipStream_t stream) {
+    Geo o;
+    int rc = check_geom(g, &o, false);
+    if (rc) return rc;
+    if (!occ_ring || !leafset) return fail(OBG_EINVAL, "occ_ring and leafset must not be NULL");
+    if (n_trees < 1) return fail(OBG_EINVAL, "n_trees must be >= 1 (got %d)", n_trees);
+    if (n_trees > 65535) return fail(OBG_EINVAL, "n_trees must be <= 65535 (got %d)", n_trees);
+    if (ring_len < n_trees) return fail(OBG_EINVAL, "ring_len %d < n_trees %d", ring_len, n_trees);
+    if (first < 0 || first >= ring_len) return fail(OBG_EINVAL, "first %d outside [0, ring_len)", first);
+    if (thr_num == 0) return fail(OBG_EINVAL, "thr_num must be >= 1 (a zero threshold keeps paths no tree has)");
+    if (thr_den == 0) return fail(OBG_EINVAL, "thr_den must be >= 1");
+    // smallest count C with C * den >= num * n_trees
+    const uint64_t need = (uint64_t)thr_num * (uint64_t)n_trees;
+    const uint64_t kmin = (need + thr_den - 1) / thr_den;
+    MergeArgs a{};
+    a.occ_ring = occ_ring;
+    a.ring_len = ring_len;
+    a.first = first;
+    a.n_trees = n_trees;
+    a.slot_words = (int64_t)o.n_regions * o.words;
+    a.words = o.words;
+    a.valid_bits_last = leaf_count(o.depth) < 32 ? leaf_count(o.depth) : 32;
+    a.empty = kmin > (uint64_t)n_trees ? 1 : 0;
+    a.kmin = a.empty ? 0u : (uint32_t)kmin;
+    a.planes = 0;
+    while ((1 << a.planes) <= n_trees) ++a.planes;
+    hipError_t e = launch_merge(a, stream);
+    if (e != hipSuccess) return hip_fail(e, "merge kernel launch");
+    return OBG_OK;
+}
+
+int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, const uint32_t *leafset,
+                 uint64_t *mask, uint32_t *occ_out, hipStream_t stream) {
+    Geo o;
+    int rc = check_geom(g, &o, true);
+    if (rc) return rc;
+    if (n_frames < 0) return fail(OBG_EINVAL, "n_frames < 0");
+    if (n_frames == 0) return OBG_OK;
+    if (!rgb || !leafset || !mask) return fail(OBG_EINVAL, "rgb, leafset and mask must not be NULL");
+    if ((uintptr_t)rgb % 16) return fail(OBG_EALIGN, "rgb must be 16-byte aligned");
+    const int mode = MODE_MASK | (occ_out ? MODE_OCC : 0);
+    return run_pixels(o, mode, rgb, n_frames, leafset, mask, occ_out, nullptr, stream);
+}
+
+const char *obg_last_error(void) { return g_err.c_str(); }
+
+const char *obg_version(void) { return "obg 0.1 gfx950"; }
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// internal.h -- launch interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.h"
+
+namespace obg {
+
+// One pass over frames in 16-pixel groups, strip by strip.  A strip is one
+// row of regions (the whole frame without regions); its tiles' bitsets live
+// in LDS while the strip is processed.
+struct StripArgs {
+    const uint8_t *rgb;
+    int64_t frame_pitch, row_pitch;
+    int32_t width, height, n_frames;
+    int32_t gpr;              // 16-pixel groups per row: 4 * ceil(width / 64)
+    int32_t strip_rows;       // rows per strip (region_h, or height)
+    int32_t n_strips;
+    int32_t reg_cols;         // regions per strip (1 without regions)
+    int32_t n_regions;
+    FastDiv div_gpr;          // group-in-strip -> row-in-strip
+    FastDiv div_tile;         // group-in-row -> region column (region_w / 16 groups)
+    int32_t span;             // groups per work item
+    int32_t spans;            // work items per (strip, frame)
+    int32_t n_items;          // n_strips * n_frames * spans
+    const uint32_t *leaf;     // [n_regions][words], key order
+    uint64_t *mask;           // [n_frames][height][mask_row_words]
+    int32_t mask_row_words;
+    uint32_t *occ;            // [n_frames][n_regions][words], zeroed, OR-ed into
+    uint32_t *counts;         // [n_frames][n_regions][8^d], zeroed, added into
+};
+
+// Per-pixel fallback for any depth 1..8 and any region size.
+struct GenericArgs {
+    const uint8_t *rgb;
+    int64_t frame_pitch, row_pitch;
+    int32_t width, height, n_frames, depth;
+    int32_t region_w, region_h, reg_cols, n_regions;
+    int32_t mask_row_words;
+    const uint32_t *leaf;
+    uint64_t *mask;
+    uint32_t *occ;
+    uint32_t *counts;
+};
+
+struct MergeArgs {
+    const uint32_t *occ_ring;
+    int32_t ring_len, first, n_trees;
+    int64_t slot_words;       // n_regions * words
+    int32_t words, valid_bits_last;  // bits used in each word (32, or 8^d for d = 1)
+    uint32_t kmin;            // keep iff count >= kmin
+    int32_t planes;           // counter bit planes: bit length of n_trees
+    int32_t empty;            // kmin > n_trees: nothing kept
+    uint32_t *leaf;
+};
+
+enum StripMode { MODE_MASK = 1, MODE_OCC = 2, MODE_COUNTS = 4 };
+
+hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block,
+                        size_t lds_bytes, hipStream_t stream);
+hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream);
+hipError_t launch_merge(const MergeArgs &a, hipStream_t stream);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
+
+}  // namespace obg

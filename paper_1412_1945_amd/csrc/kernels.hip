@@ -1,0 +1,356 @@
+// kernels.hip -- gfx950 kernels of octree background modelling.
+//
+// strip_kernel  one pass over 16-pixel groups (48 contiguous bytes = three
+//               16-byte loads per lane).  Per pixel: three bit-field extracts
+//               give the top d bits of R, G, B (the depth-d node of the
+//               pixel's octree path, Algorithm 1 with the pruning of
+//               Section 2), two shift-ors give its LDS index, then
+//                 MASK   test the bit in the merged leaf set (Algorithm 3),
+//                        16 results per lane packed into one 16-bit store;
+//                 OCC    set the bit in this frame's LDS occupancy bitset
+//                        (test first, atomic OR only when unset); the bitset
+//                        is OR-ed into HBM once per (frame, strip) segment;
+//                 COUNTS add the pixel to the key's counter (runs of equal
+//                        keys inside a lane are added with one atomic).
+// generic_kernel per-pixel fallback for d = 7, 8 and region widths that are
+//               not a multiple of 16 pixels; bitsets stay in HBM/L2.
+// merge_kernel  per 32 keys: bit-sliced counters of the window's bitsets and
+//               a bit-sliced compare against the frame-count threshold
+//               (Algorithm 2 in closed form).
+#include "internal.h"
+
+namespace obg {
+
+// ---------------------------------------------------------------------------
+// LDS <-> HBM bitset conversion (key order in HBM, concat order in LDS)
+
+template <int D>
+__device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, uint32_t *lds,
+                                            int n_words, int tid, int nt) {
+    constexpr int WORDS = leaf_words(D);
+    constexpr int LC = leaf_count(D);
+    constexpr int NB = LC < 32 ? LC : 32;
+    for (int i = tid; i < n_words; i += nt) lds[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n_words; i += nt) {
+        const int c = i / WORDS;
+        const int kw = i - c * WORDS;
+        uint32_t bits = leaf[i];
+        if (LC < 32) bits &= (1u << (LC & 31)) - 1u;
+        if (bits == 0) continue;
+        const uint32_t jbase = concat_from_key((uint32_t)kw << 5, D);
+        uint32_t *tile = lds + c * WORDS;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if ((bits >> b) & 1u) {
+                const uint32_t j = jbase | concat_from_key((uint32_t)b, D);
+                atomicOr(&tile[j >> 5], 1u << (j & 31));
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int D>
+__device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__restrict__ occ,
+                                             int n_words, int tid, int nt) {
+    constexpr int WORDS = leaf_words(D);
+    constexpr int LC = leaf_count(D);
+    constexpr int NB = LC < 32 ? LC : 32;
+    for (int i = tid; i < n_words; i += nt) {
+        const int c = i / WORDS;
+        const int kw = i - c * WORDS;
+        const uint32_t jbase = concat_from_key((uint32_t)kw << 5, D);
+        const uint32_t *tile = lds + c * WORDS;
+        uint32_t out = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint32_t j = jbase | concat_from_key((uint32_t)b, D);
+            out |= ((tile[j >> 5] >> (j & 31)) & 1u) << b;
+        }
+        if (out) atomicOr(&occ[i], out);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-group work
+
+template <int D, int MODE, bool FULL>
+__device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nvalid,
+                                                 const uint32_t *leaf_tile, uint32_t *occ_tile,
+                                                 uint32_t *__restrict__ cnt) {
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    constexpr bool OCC = (MODE & MODE_OCC) != 0;
+    constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
+    uint32_t present = 0;
+    uint32_t run_j = 0xFFFFFFFFu, run_n = 0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        if (FULL || p < nvalid) {
+            const uint32_t j = concat_index<D>(u, p);
+            if (MASK) present |= ((leaf_tile[j >> 5] >> (j & 31)) & 1u) << p;
+            if (OCC) {
+                uint32_t *w = &occ_tile[j >> 5];
+                const uint32_t m = 1u << (j & 31);
+                if ((*w & m) == 0) atomicOr(w, m);
+            }
+            if (CNT) {
+                if (j == run_j) {
+                    ++run_n;
+                } else {
+                    if (run_n) atomicAdd(&cnt[key_from_concat(run_j, D)], run_n);
+                    run_j = j;
+                    run_n = 1;
+                }
+            }
+        }
+    }
+    if (CNT && run_n) atomicAdd(&cnt[key_from_concat(run_j, D)], run_n);
+    return present;
+}
+
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
+    extern __shared__ uint32_t lds[];
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    constexpr bool OCC = (MODE & MODE_OCC) != 0;
+    constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
+    constexpr int WORDS = leaf_words(D);
+    constexpr int LC = leaf_count(D);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int strip_words = a.reg_cols * WORDS;
+    uint32_t *leaf_lds = lds;
+    uint32_t *occ_lds = lds + (MASK ? strip_words : 0);
+
+    const int i0 = (int)((int64_t)a.n_items * blockIdx.x / gridDim.x);
+    const int i1 = (int)((int64_t)a.n_items * (blockIdx.x + 1) / gridDim.x);
+    int cur_s = -1, cur_f = -1;
+    for (int it = i0; it < i1; ++it) {
+        const int sf = it / a.spans;
+        const int t = it - sf * a.spans;
+        const int s = sf / a.n_frames;
+        const int f = sf - s * a.n_frames;
+        const bool new_seg = (s != cur_s) || (f != cur_f);
+        if (OCC && new_seg && cur_f >= 0) {
+            __syncthreads();
+            occ_from_lds<D>(occ_lds,
+                            a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * a.reg_cols) * WORDS,
+                            strip_words, tid, nt);
+        }
+        if (MASK && s != cur_s) {
+            __syncthreads();
+            leaf_to_lds<D>(a.leaf + (int64_t)s * a.reg_cols * WORDS, leaf_lds, strip_words, tid, nt);
+        }
+        if (OCC && new_seg) {
+            __syncthreads();
+            for (int i = tid; i < strip_words; i += nt) occ_lds[i] = 0;
+            __syncthreads();
+        }
+        cur_s = s;
+        cur_f = f;
+
+        const int row0 = s * a.strip_rows;
+        const int rows = min(a.strip_rows, a.height - row0);
+        const int gcount = rows * a.gpr;
+        const int gb = t * a.span;
+        const int ge = min(gb + a.span, gcount);
+        const uint8_t *fbase = a.rgb + (int64_t)f * a.frame_pitch + (int64_t)row0 * a.row_pitch;
+        uint8_t *mbase = MASK ? reinterpret_cast<uint8_t *>(
+                                    a.mask + ((int64_t)f * a.height + row0) * a.mask_row_words)
+                              : nullptr;
+        uint32_t *cbase = CNT ? a.counts + ((int64_t)f * a.n_regions + (int64_t)s * a.reg_cols) * LC
+                              : nullptr;
+        for (int g = gb + tid; g < ge; g += nt) {
+            const uint32_t yr = fdiv((uint32_t)g, a.div_gpr);
+            const uint32_t gx = (uint32_t)g - yr * (uint32_t)a.gpr;
+            const int x0 = (int)gx * 16;
+            const uint8_t *src = fbase + (int64_t)yr * a.row_pitch + 48 * (int64_t)gx;
+            uint32_t present = 0, valid = 0;
+            if (x0 < a.width) {
+                const int c = (int)fdiv(gx, a.div_tile);
+                const uint32_t *leaf_tile = leaf_lds + c * WORDS;
+                uint32_t *occ_tile = occ_lds + c * WORDS;
+                uint32_t *cnt = CNT ? cbase + (int64_t)c * LC : nullptr;
+                uint32_t u[12];
+                if (x0 + 16 <= a.width) {
+                    load48(src, u);
+                    present = group_pixels<D, MODE, true>(u, 16, leaf_tile, occ_tile, cnt);
+                    valid = 0xFFFFu;
+                } else {
+                    const int nv = a.width - x0;
+                    const int chunks = (3 * nv + 15) / 16;
+                    const uint4 *q = reinterpret_cast<const uint4 *>(src);
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        uint4 v = make_uint4(0, 0, 0, 0);
+                        if (k < chunks) v = q[k];
+                        u[4 * k + 0] = v.x; u[4 * k + 1] = v.y;
+                        u[4 * k + 2] = v.z; u[4 * k + 3] = v.w;
+                    }
+                    present = group_pixels<D, MODE, false>(u, nv, leaf_tile, occ_tile, cnt);
+                    valid = (1u << nv) - 1u;
+                }
+            }
+            if (MASK) {
+                *reinterpret_cast<uint16_t *>(mbase + (int64_t)yr * a.mask_row_words * 8 + 2 * (int64_t)gx) =
+                    (uint16_t)(~present & valid);
+            }
+        }
+    }
+    if (OCC && cur_f >= 0) {
+        __syncthreads();
+        occ_from_lds<D>(occ_lds,
+                        a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * a.reg_cols) * WORDS,
+                        strip_words, tid, nt);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Generic per-pixel kernel: one thread per 64-pixel mask word.
+
+__global__ __launch_bounds__(256) void generic_kernel(GenericArgs a, int mode) {
+    const int words = leaf_words(a.depth);
+    const int64_t lc = (int64_t)leaf_count(a.depth);
+    const int64_t total = (int64_t)a.n_frames * a.height * a.mask_row_words;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t fy = t / a.mask_row_words;
+        const int wx = (int)(t - fy * a.mask_row_words);
+        const int f = (int)(fy / a.height);
+        const int y = (int)(fy - (int64_t)f * a.height);
+        const uint8_t *row = a.rgb + (int64_t)f * a.frame_pitch + (int64_t)y * a.row_pitch;
+        const int ry = a.region_h ? y / a.region_h : 0;
+        uint64_t m = 0;
+        const int xe = min(a.width, (wx + 1) * 64);
+        for (int x = wx * 64; x < xe; ++x) {
+            const uint32_t k = path_key(row[3 * x], row[3 * x + 1], row[3 * x + 2], a.depth);
+            const int reg = a.region_w ? ry * a.reg_cols + x / a.region_w : 0;
+            if (mode & MODE_MASK) {
+                const uint32_t w = a.leaf[(int64_t)reg * words + (k >> 5)];
+                if (((w >> (k & 31)) & 1u) == 0) m |= 1ull << (x & 63);
+            }
+            if (mode & MODE_OCC) {
+                uint32_t *w = &a.occ[((int64_t)f * a.n_regions + reg) * words + (k >> 5)];
+                const uint32_t bit = 1u << (k & 31);
+                if ((__atomic_load_n(w, __ATOMIC_RELAXED) & bit) == 0) atomicOr(w, bit);
+            }
+            if (mode & MODE_COUNTS) atomicAdd(&a.counts[((int64_t)f * a.n_regions + reg) * lc + k], 1u);
+        }
+        if (mode & MODE_MASK) a.mask[t] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Merge: bit-sliced frame counts, one thread per 32 keys.
+
+__global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= a.slot_words) return;
+    const uint32_t valid = a.valid_bits_last >= 32 ? 0xFFFFFFFFu : ((1u << a.valid_bits_last) - 1u);
+    if (a.empty) {
+        a.leaf[i] = 0;
+        return;
+    }
+    uint32_t c[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) c[b] = 0;
+    int slot = a.first;
+    for (int t = 0; t < a.n_trees; ++t) {
+        uint32_t carry = a.occ_ring[(int64_t)slot * a.slot_words + i] & valid;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            if (b < a.planes) {
+                const uint32_t tmp = c[b] & carry;
+                c[b] ^= carry;
+                carry = tmp;
+            }
+        }
+        if (++slot == a.ring_len) slot = 0;
+    }
+    // bit-sliced count >= kmin
+    uint32_t ge = 0, eq = 0xFFFFFFFFu;
+#pragma unroll
+    for (int b = 15; b >= 0; --b) {
+        if ((a.kmin >> b) & 1u) {
+            eq &= c[b];
+        } else {
+            ge |= eq & c[b];
+            eq &= ~c[b];
+        }
+    }
+    ge |= eq;
+    a.leaf[i] = ge & valid;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+
+template <int D>
+static hipError_t launch_strip_d(int mode, const StripArgs &a, int grid, int block, size_t lds,
+                                 hipStream_t st) {
+    switch (mode) {
+        case MODE_MASK:
+            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK>), dim3(grid), dim3(block), lds, st, a);
+            break;
+        case MODE_OCC:
+            hipLaunchKernelGGL((strip_kernel<D, MODE_OCC>), dim3(grid), dim3(block), lds, st, a);
+            break;
+        case MODE_MASK | MODE_OCC:
+            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK | MODE_OCC>), dim3(grid), dim3(block), lds, st, a);
+            break;
+        case MODE_OCC | MODE_COUNTS:
+            hipLaunchKernelGGL((strip_kernel<D, MODE_OCC | MODE_COUNTS>), dim3(grid), dim3(block), lds, st, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block,
+                        size_t lds_bytes, hipStream_t stream) {
+    switch (depth) {
+        case 1: return launch_strip_d<1>(mode, a, grid, block, lds_bytes, stream);
+        case 2: return launch_strip_d<2>(mode, a, grid, block, lds_bytes, stream);
+        case 3: return launch_strip_d<3>(mode, a, grid, block, lds_bytes, stream);
+        case 4: return launch_strip_d<4>(mode, a, grid, block, lds_bytes, stream);
+        case 5: return launch_strip_d<5>(mode, a, grid, block, lds_bytes, stream);
+        case 6: return launch_strip_d<6>(mode, a, grid, block, lds_bytes, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream) {
+    const int64_t total = (int64_t)a.n_frames * a.height * a.mask_row_words;
+    if (total == 0) return hipSuccess;
+    const int block = 256;
+    const int64_t want = (total + block - 1) / block;
+    const int grid = (int)(want < 65536 ? want : 65536);
+    hipLaunchKernelGGL(generic_kernel, dim3(grid), dim3(block), 0, stream, a, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(const MergeArgs &a, hipStream_t stream) {
+    if (a.slot_words == 0) return hipSuccess;
+    const int block = 256;
+    const int64_t grid = (a.slot_words + block - 1) / block;
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)grid), dim3(block), 0, stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int block = 256;
+    const int64_t want = (n + block - 1) / block;
+    const int grid = (int)(want < 8192 ? want : 8192);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid), dim3(block), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace obg

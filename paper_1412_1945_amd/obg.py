@@ -1,0 +1,196 @@
+"""Python binding of libobg.so (ctypes; argument marshalling only).
+
+Every function has the name of the C entry point it calls.  Tensors are torch
+tensors on the GPU; the library receives their device pointers and the current
+HIP stream, and all the work runs in the library's kernels.  A missing or
+unloadable library raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libobg.so")
+
+OBG_OK, OBG_EINVAL, OBG_EALIGN, OBG_EHIP, OBG_ENOMEM = 0, -1, -2, -3, -4
+
+
+class ObgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"obg error {code}: {msg}")
+        self.code = code
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("row_pitch", ctypes.c_int64), ("frame_pitch", ctypes.c_int64),
+        ("depth", ctypes.c_int32),
+        ("region_w", ctypes.c_int32), ("region_h", ctypes.c_int32),
+    ]
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python paper_1412_1945_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        G = ctypes.POINTER(Geom)
+        sigs = {
+            "obg_num_regions": (I64, [G]),
+            "obg_occ_words": (I64, [G]),
+            "obg_mask_words": (I64, [G]),
+            "obg_train_frame": (ctypes.c_int, [G, P, I32, P, P, P]),
+            "obg_merge": (ctypes.c_int, [G, P, I32, I32, I32, U32, U32, P, P]),
+            "obg_classify": (ctypes.c_int, [G, P, I32, P, P, P, P]),
+            "obg_last_error": (ctypes.c_char_p, []),
+            "obg_version": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sigs.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
+            "obg_merge", "obg_classify", "obg_last_error", "obg_version"]
+
+
+@dataclass
+class FrameGeom:
+    width: int
+    height: int
+    depth: int
+    row_pitch: int = 0
+    frame_pitch: int = 0
+    region_w: int = 0
+    region_h: int = 0
+
+    def __post_init__(self):
+        if self.row_pitch == 0:
+            self.row_pitch = ((3 * self.width + 15) // 16) * 16
+        if self.frame_pitch == 0:
+            self.frame_pitch = self.height * self.row_pitch
+
+    def c(self) -> Geom:
+        return Geom(self.width, self.height, self.row_pitch, self.frame_pitch, self.depth,
+                    self.region_w, self.region_h)
+
+    @property
+    def n_regions(self) -> int:
+        if self.region_w == 0:
+            return 1
+        return (-(-self.width // self.region_w)) * (-(-self.height // self.region_h))
+
+    @property
+    def words(self) -> int:
+        return max(1, (1 << (3 * self.depth)) // 32)
+
+    @property
+    def mask_row_words(self) -> int:
+        return (self.width + 63) // 64
+
+
+def _check(rc: int):
+    if rc != OBG_OK:
+        raise ObgError(rc, load().obg_last_error().decode())
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, numel: int, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {numel}")
+
+
+def _frames_ok(g: FrameGeom, rgb: torch.Tensor, n_frames: int):
+    _need(rgb, torch.uint8, 0, "rgb")
+    need = n_frames * g.frame_pitch
+    if rgb.numel() < need:
+        raise ValueError(f"rgb holds {rgb.numel()} bytes, {n_frames} frames need {need}")
+
+
+def obg_num_regions(g: FrameGeom) -> int:
+    return load().obg_num_regions(ctypes.byref(g.c()))
+
+
+def obg_occ_words(g: FrameGeom) -> int:
+    return load().obg_occ_words(ctypes.byref(g.c()))
+
+
+def obg_mask_words(g: FrameGeom) -> int:
+    return load().obg_mask_words(ctypes.byref(g.c()))
+
+
+def obg_train_frame(g: FrameGeom, rgb: torch.Tensor, n_frames: int, occ: torch.Tensor,
+                    counts: Optional[torch.Tensor] = None, stream=None):
+    _frames_ok(g, rgb, n_frames)
+    _need(occ, torch.int32, n_frames * g.n_regions * g.words, "occ")
+    if counts is not None:
+        _need(counts, torch.int32, n_frames * g.n_regions * (1 << (3 * g.depth)), "counts")
+    _check(load().obg_train_frame(ctypes.byref(g.c()), _ptr(rgb), n_frames, _ptr(occ),
+                                  _ptr(counts), _stream(stream)))
+
+
+def obg_merge(g: FrameGeom, occ_ring: torch.Tensor, ring_len: int, first: int, n_trees: int,
+              thr_num: int, thr_den: int, leafset: torch.Tensor, stream=None):
+    _need(occ_ring, torch.int32, ring_len * g.n_regions * g.words, "occ_ring")
+    _need(leafset, torch.int32, g.n_regions * g.words, "leafset")
+    _check(load().obg_merge(ctypes.byref(g.c()), _ptr(occ_ring), ring_len, first, n_trees,
+                            thr_num, thr_den, _ptr(leafset), _stream(stream)))
+
+
+def obg_classify(g: FrameGeom, rgb: torch.Tensor, n_frames: int, leafset: torch.Tensor,
+                 mask: torch.Tensor, occ_out: Optional[torch.Tensor] = None, stream=None):
+    _frames_ok(g, rgb, n_frames)
+    _need(leafset, torch.int32, g.n_regions * g.words, "leafset")
+    _need(mask, torch.int64, n_frames * g.height * g.mask_row_words, "mask")
+    if occ_out is not None:
+        _need(occ_out, torch.int32, n_frames * g.n_regions * g.words, "occ_out")
+    _check(load().obg_classify(ctypes.byref(g.c()), _ptr(rgb), n_frames, _ptr(leafset),
+                               _ptr(mask), _ptr(occ_out), _stream(stream)))
+
+
+def obg_version() -> str:
+    return load().obg_version().decode()
+
+
+# -- convenience allocation helpers (torch owns the memory) ------------------
+
+def empty_occ(g: FrameGeom, n_frames: int, device="cuda") -> torch.Tensor:
+    return torch.empty((n_frames, g.n_regions, g.words), dtype=torch.int32, device=device)
+
+
+def empty_mask(g: FrameGeom, n_frames: int, device="cuda") -> torch.Tensor:
+    return torch.empty((n_frames, g.height, g.mask_row_words), dtype=torch.int64, device=device)
+
+
+def empty_leafset(g: FrameGeom, device="cuda") -> torch.Tensor:
+    return torch.empty((g.n_regions, g.words), dtype=torch.int32, device=device)

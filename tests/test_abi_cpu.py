@@ -1,0 +1,126 @@
+"""The C-ABI library loads, exports what include/obg.h declares, and rejects
+bad arguments before touching the GPU (no kernel is launched here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "obg.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1412_1945_amd import obg
+    if not os.path.exists(obg.LIB_PATH):
+        from paper_1412_1945_amd import build
+        build.build()
+    return obg
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(obg_[a-z_0-9]+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declares_entry_points():
+    names = declared_functions()
+    for n in ["obg_train_frame", "obg_merge", "obg_classify", "obg_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    L = ctypes.CDLL(lib.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert set(declared_functions()) <= set(lib.exported_symbols()) | {"obg_batch_create", "obg_batch_run", "obg_batch_destroy", "obg_batch_info", "obg_serve_run"}
+
+
+def test_sizes(lib):
+    g = lib.FrameGeom(160, 120, 4)
+    assert lib.obg_num_regions(g) == 1
+    assert lib.obg_occ_words(g) == 128
+    assert lib.obg_mask_words(g) == 120 * 3
+    g = lib.FrameGeom(3840, 2160, 4, region_w=32, region_h=32)
+    assert lib.obg_num_regions(g) == 120 * 68
+    assert lib.obg_occ_words(g) == 120 * 68 * 128
+    g = lib.FrameGeom(10, 10, 1)
+    assert lib.obg_occ_words(g) == 1
+    g = lib.FrameGeom(10, 10, 8)
+    assert lib.obg_occ_words(g) == (1 << 24) // 32
+    bad = lib.FrameGeom(10, 10, 9)
+    assert lib.obg_num_regions(bad) == -1
+
+
+def _raw(lib):
+    return lib.load()
+
+
+def _geom(lib, **kw):
+    base = dict(width=64, height=8, row_pitch=192, frame_pitch=192 * 8, depth=4, region_w=0, region_h=0)
+    base.update(kw)
+    return lib.Geom(**base)
+
+
+FAKE = ctypes.c_void_p(0x100000)   # never dereferenced: every case fails validation first
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(depth=0), -1), (dict(depth=9), -1), (dict(width=0), -1), (dict(height=0), -1),
+    (dict(row_pitch=176), -1), (dict(frame_pitch=100), -1),
+    (dict(row_pitch=200, frame_pitch=1600), -2), (dict(frame_pitch=192 * 8 + 8), -2),
+    (dict(region_w=16, region_h=0), -1), (dict(region_w=-1, region_h=4), -1),
+])
+def test_train_rejects_bad_geometry(lib, kw, code):
+    L = _raw(lib)
+    g = _geom(lib, **kw)
+    rc = L.obg_train_frame(ctypes.byref(g), FAKE, 1, FAKE, None, None)
+    assert rc == code, L.obg_last_error()
+    assert L.obg_last_error()
+
+
+def test_train_rejects_null_and_unaligned(lib):
+    L = _raw(lib)
+    g = _geom(lib)
+    assert L.obg_train_frame(ctypes.byref(g), None, 1, FAKE, None, None) == -1
+    assert L.obg_train_frame(ctypes.byref(g), FAKE, 1, None, None, None) == -1
+    assert L.obg_train_frame(ctypes.byref(g), ctypes.c_void_p(0x100004), 1, FAKE, None, None) == -2
+    assert L.obg_train_frame(ctypes.byref(g), FAKE, -1, FAKE, None, None) == -1
+    assert L.obg_train_frame(None, FAKE, 1, FAKE, None, None) == -1
+    # zero frames: nothing to do, nothing enqueued
+    assert L.obg_train_frame(ctypes.byref(g), None, 0, None, None, None) == 0
+
+
+@pytest.mark.parametrize("args,code", [
+    ((4, 0, 0, 1, 2), -1),       # n_trees < 1
+    ((4, 0, 5, 1, 2), -1),       # n_trees > ring_len
+    ((4, 4, 2, 1, 2), -1),       # first outside the ring
+    ((4, -1, 2, 1, 2), -1),
+    ((4, 0, 2, 0, 2), -1),       # zero threshold
+    ((4, 0, 2, 1, 0), -1),       # zero denominator
+    ((70000, 0, 70000, 1, 2), -1),  # too many trees for the counters
+])
+def test_merge_rejects_bad_window(lib, args, code):
+    L = _raw(lib)
+    g = _geom(lib)
+    ring, first, n, num, den = args
+    rc = L.obg_merge(ctypes.byref(g), FAKE, ring, first, n, num, den, FAKE, None)
+    assert rc == code, L.obg_last_error()
+
+
+def test_classify_rejects_null(lib):
+    L = _raw(lib)
+    g = _geom(lib)
+    assert L.obg_classify(ctypes.byref(g), FAKE, 1, None, FAKE, None, None) == -1
+    assert L.obg_classify(ctypes.byref(g), FAKE, 1, FAKE, None, None, None) == -1
+    assert L.obg_classify(ctypes.byref(g), None, 0, None, None, None, None) == 0
+
+
+def test_binding_refuses_cpu_tensors(lib):
+    import torch
+    g = lib.FrameGeom(16, 4, 3)
+    with pytest.raises(ValueError):
+        lib.obg_train_frame(g, torch.zeros(16 * 4 * 3, dtype=torch.uint8), 1,
+                            torch.zeros(16, dtype=torch.int32))

@@ -1,0 +1,208 @@
+"""GPU parity: libobg.so (through the C ABI) against the CPU oracle, bit for bit.
+
+Inputs are seeded: random tiny frames (numpy) and the synthetic streams of
+synth.frames; the oracle sees the same bytes as the GPU.  Every comparison is
+exact -- occupancy bitsets, pixel counts, merged leaf sets and masks are
+integers with one correct value each.
+"""
+import numpy as np
+import pytest
+import torch
+
+import brute
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(oracle_lib):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_1945_amd import obg
+    obg.load()
+    return obg, oracle_lib
+
+
+def u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def u64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def upload(frames, frame_pitch=None):
+    """Stack host frames [H, row_pitch] into one device buffer with frame_pitch."""
+    h, rp = frames[0].shape
+    fp = frame_pitch or h * rp
+    buf = np.zeros((len(frames), fp), dtype=np.uint8)
+    for i, f in enumerate(frames):
+        buf[i, : h * rp] = f.reshape(-1)
+    return torch.from_numpy(buf).cuda()
+
+
+def run_pipeline(obg, g, dev_train, T, dev_test, n_test, num, den, counts=False):
+    occ = obg.empty_occ(g, T)
+    cnt = torch.empty((T, g.n_regions, 1 << (3 * g.depth)), dtype=torch.int32, device="cuda") if counts else None
+    leaf = obg.empty_leafset(g)
+    mask = obg.empty_mask(g, n_test)
+    obg.obg_train_frame(g, dev_train, T, occ, cnt)
+    obg.obg_merge(g, occ, T, 0, T, num, den, leaf)
+    obg.obg_classify(g, dev_test, n_test, leaf, mask)
+    torch.cuda.synchronize()
+    return occ, cnt, leaf, mask
+
+
+def check_against_oracle(env, W, H, d, frames, T, num, den, rw=0, rh=0, row_pitch=None,
+                         frame_pitch=None, counts=True, label=""):
+    obg, O = env
+    rp = row_pitch or frames[0].shape[1]
+    g = obg.FrameGeom(W, H, d, row_pitch=rp, frame_pitch=frame_pitch or 0, region_w=rw, region_h=rh)
+    print(f"[case] {label} W={W} H={H} d={d} T={T} thr={num}/{den} region={rw}x{rh} pitch={rp}", flush=True)
+    dtrain = upload(frames[:T], g.frame_pitch)
+    dtest = upload(frames[T:], g.frame_pitch)
+    n_test = len(frames) - T
+    occ, cnt, leaf, mask = run_pipeline(obg, g, dtrain, T, dtest, n_test, num, den, counts)
+    f = O.Forest(W, H, d, rw, rh)
+    idx = f.add_frames(frames[:T], store_levels=8 if W * H <= 4096 else None)
+    for i in idx:
+        o, c = f.export(i, with_counts=True)
+        assert np.array_equal(u32(occ[i]).reshape(o.shape), o), f"{label} occupancy frame {i}"
+        if counts:
+            assert np.array_equal(u32(cnt[i]).reshape(c.shape), c), f"{label} counts frame {i}"
+    model = f.merge(idx, num, den)
+    assert np.array_equal(u32(leaf).reshape(model.n_regions, -1), model.leafset()), f"{label} leaf set"
+    for i in range(n_test):
+        want = model.classify(frames[T + i])
+        assert np.array_equal(u64(mask[i]).reshape(want.shape), want), f"{label} mask frame {i}"
+    return occ, leaf, mask
+
+
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", range(1, 9))
+def test_all_depths_ragged_widths(env, d):
+    rng = np.random.default_rng(d)
+    for W, H in [(1, 1), (17, 3), (64, 2), (100, 5), (130, 4)]:
+        rp = ((3 * W + 15) // 16) * 16
+        frames = brute.tiny_frames(rng, 6, W, H, n_colours=7, row_pitch=rp)
+        check_against_oracle(env, W, H, d, frames, 4, 1, 2, label=f"depth{d}", counts=(d <= 6))
+
+
+@pytest.mark.parametrize("W", [15, 16, 33, 48, 63, 65, 127, 160, 193])
+def test_widths_and_padding(env, W):
+    rng = np.random.default_rng(W)
+    H = 9
+    rp = ((3 * W + 15) // 16) * 16 + 32          # extra row padding
+    frames = brute.tiny_frames(rng, 7, W, H, n_colours=10, row_pitch=rp)
+    for f in frames:
+        f[:, 3 * W:] = 0xAB                     # padding bytes must not matter
+    check_against_oracle(env, W, H, 5, frames, 5, 2, 5, row_pitch=rp,
+                         frame_pitch=H * rp + 48, label="pad")
+
+
+@pytest.mark.parametrize("num,den", [(1, 10), (3, 10), (1, 2), (7, 10), (1, 1), (3, 2)])
+def test_thresholds(env, num, den):
+    rng = np.random.default_rng(num * 100 + den)
+    W, H = 96, 12
+    frames = brute.tiny_frames(rng, 14, W, H, n_colours=24)
+    check_against_oracle(env, W, H, 3, frames, 10, num, den, label="thr")
+
+
+@pytest.mark.parametrize("rw,rh,d", [(32, 32, 4), (16, 8, 3), (48, 20, 5), (24, 20, 4), (32, 16, 6), (7, 5, 2), (16, 4, 7)])
+def test_regions(env, rw, rh, d):
+    rng = np.random.default_rng(rw * rh + d)
+    W, H = 200, 70
+    frames = brute.tiny_frames(rng, 6, W, H, n_colours=12)
+    check_against_oracle(env, W, H, d, frames, 4, 1, 2, rw=rw, rh=rh, label="region",
+                         counts=(d <= 6))
+
+
+def test_cfg0_full(env):
+    """The small plain workload end to end; frames made on the GPU."""
+    from synth.frames import cfg0, make_frames
+    obg, O = env
+    wl = cfg0()
+    s = wl.streams[0]
+    dev = make_frames(s, range(s.n_frames), device="cuda")
+    host = make_frames(s, [0, s.n_train, s.n_frames - 1], device="cpu")
+    assert torch.equal(dev[[0, s.n_train, s.n_frames - 1]].cpu(), host), "generator differs between devices"
+    frames = list(dev.cpu().numpy())
+    num, den = wl.thr[0]
+    check_against_oracle(env, s.width, s.height, wl.depth[0], frames, s.n_train, num, den, label="cfg0")
+
+
+def test_merge_ring_windows(env):
+    """Merge over windows of a ring of synthetic bitsets, including wrap-around."""
+    obg, O = env
+    rng = np.random.default_rng(77)
+    for d, nreg, ring, dens in [(2, 3, 9, 0.5), (4, 2, 60, 0.3), (5, 1, 120, 0.6), (6, 1, 40, 0.05), (1, 5, 7, 0.5)]:
+        W = 8
+        g = obg.FrameGeom(W * nreg, 8, d, region_w=(W if nreg > 1 else 0), region_h=(8 if nreg > 1 else 0))
+        words = g.words
+        lc = 1 << (3 * d)
+        bits = rng.random((ring, nreg, max(lc, 32))) < dens
+        bits[:, :, lc:] = False
+        occ = np.packbits(bits, axis=-1, bitorder="little").view(np.uint32).reshape(ring, nreg, words)
+        docc = torch.from_numpy(occ.view(np.int32).copy()).cuda()
+        for first, n, num, den in [(0, ring, 1, 2), (ring - 3, min(ring, 5), 3, 10), (1, ring - 1, 7, 10),
+                                   (ring // 2, ring, 1, 1), (0, 1, 1, 2), (ring - 1, ring, 2, 3)]:
+            print(f"[case] merge d={d} nreg={nreg} ring={ring} first={first} n={n} thr={num}/{den}", flush=True)
+            leaf = obg.empty_leafset(g)
+            obg.obg_merge(g, docc, ring, first, n, num, den, leaf)
+            torch.cuda.synchronize()
+            f = O.Forest(g.width, g.height, d, g.region_w, g.region_h)
+            idx = [f.add_occupancy(occ[(first + t) % ring]) for t in range(n)]
+            want = f.merge(idx, num, den).leafset()
+            assert np.array_equal(u32(leaf).reshape(want.shape), want)
+
+
+def test_fused_classify_occupancy(env):
+    obg, O = env
+    rng = np.random.default_rng(3)
+    for W, H, d, rw, rh in [(160, 40, 4, 0, 0), (96, 33, 6, 0, 0), (128, 64, 3, 32, 32), (50, 10, 7, 0, 0)]:
+        rp = ((3 * W + 15) // 16) * 16
+        frames = brute.tiny_frames(rng, 5, W, H, n_colours=9, row_pitch=rp)
+        g = obg.FrameGeom(W, H, d, region_w=rw, region_h=rh)
+        print(f"[case] fused W={W} H={H} d={d} region={rw}x{rh}", flush=True)
+        dev = upload(frames, g.frame_pitch)
+        occ_t = obg.empty_occ(g, 5)
+        obg.obg_train_frame(g, dev, 5, occ_t)
+        leaf = obg.empty_leafset(g)
+        obg.obg_merge(g, occ_t, 5, 0, 3, 1, 2, leaf)
+        mask_a = obg.empty_mask(g, 5)
+        mask_b = obg.empty_mask(g, 5)
+        occ_c = obg.empty_occ(g, 5)
+        obg.obg_classify(g, dev, 5, leaf, mask_a)
+        obg.obg_classify(g, dev, 5, leaf, mask_b, occ_c)
+        torch.cuda.synchronize()
+        assert torch.equal(mask_a, mask_b)
+        assert torch.equal(occ_t, occ_c)
+
+
+def test_repeat_runs_identical(env):
+    """Results are exact integers; repeated launches must give identical bytes
+    (a race in LDS or in the atomics would show here)."""
+    obg, O = env
+    rng = np.random.default_rng(99)
+    W, H = 480, 270
+    frames = brute.tiny_frames(rng, 8, W, H, n_colours=40)
+    for d, rw, rh in [(4, 0, 0), (5, 0, 0), (6, 0, 0), (4, 32, 32)]:
+        g = obg.FrameGeom(W, H, d, region_w=rw, region_h=rh)
+        dev = upload(frames, g.frame_pitch)
+        outs = []
+        for rep in range(3):
+            occ, _, leaf, mask = run_pipeline(obg, g, dev, 6, dev[6:], 2, 1, 2)
+            outs.append((occ.clone(), leaf.clone(), mask.clone()))
+        for o in outs[1:]:
+            assert all(torch.equal(a, b) for a, b in zip(outs[0], o))
+
+
+def test_zero_frames_is_noop(env):
+    obg, O = env
+    g = obg.FrameGeom(64, 4, 4)
+    occ = torch.full((1, 1, g.words), 7, dtype=torch.int32, device="cuda")
+    dummy = torch.zeros(64 * 3 * 4, dtype=torch.uint8, device="cuda")
+    obg.obg_train_frame(g, dummy, 0, occ)
+    torch.cuda.synchronize()
+    assert int(occ[0, 0, 0]) == 7
