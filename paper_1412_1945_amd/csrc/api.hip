@@ -238,6 +238,7 @@ int obg_merge(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len, int
     a.valid_bits_last = leaf_count(o.depth) < 32 ? leaf_count(o.depth) : 32;
     a.empty = kmin > (uint64_t)n_trees ? 1 : 0;
     a.kmin = a.empty ? 0u : (uint32_t)kmin;
+    a.leaf = leafset;
     a.planes = 0;
     while ((1 << a.planes) <= n_trees) ++a.planes;
     hipError_t e = launch_merge(a, stream);

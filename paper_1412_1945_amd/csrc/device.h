@@ -60,8 +60,8 @@ inline FastDiv make_fastdiv(uint32_t d) {
     return f;
 }
 
-__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
-    uint32_t t = __umulhi(f.m, n);
+__host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+    uint32_t t = (uint32_t)(((uint64_t)f.m * n) >> 32);
     return (t + ((n - t) >> f.s1)) >> f.s2;
 }
 

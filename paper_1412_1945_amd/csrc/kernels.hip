@@ -313,8 +313,19 @@ static hipError_t launch_strip_d(int mode, const StripArgs &a, int grid, int blo
     return hipGetLastError();
 }
 
+// Every pointer a mode writes or reads must be set; a launch with a missing
+// one is refused instead of faulting on the device.
+static bool strip_pointers_ok(int mode, const StripArgs &a) {
+    if (!a.rgb) return false;
+    if ((mode & MODE_MASK) && (!a.leaf || !a.mask)) return false;
+    if ((mode & MODE_OCC) && !a.occ) return false;
+    if ((mode & MODE_COUNTS) && !a.counts) return false;
+    return true;
+}
+
 hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block,
                         size_t lds_bytes, hipStream_t stream) {
+    if (!strip_pointers_ok(mode, a) || grid < 1 || block != 256) return hipErrorInvalidValue;
     switch (depth) {
         case 1: return launch_strip_d<1>(mode, a, grid, block, lds_bytes, stream);
         case 2: return launch_strip_d<2>(mode, a, grid, block, lds_bytes, stream);
@@ -327,6 +338,9 @@ hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int b
 }
 
 hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream) {
+    if (!a.rgb || ((mode & MODE_MASK) && (!a.leaf || !a.mask)) || ((mode & MODE_OCC) && !a.occ) ||
+        ((mode & MODE_COUNTS) && !a.counts))
+        return hipErrorInvalidValue;
     const int64_t total = (int64_t)a.n_frames * a.height * a.mask_row_words;
     if (total == 0) return hipSuccess;
     const int block = 256;
@@ -337,6 +351,8 @@ hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream) {
 }
 
 hipError_t launch_merge(const MergeArgs &a, hipStream_t stream) {
+    if (!a.occ_ring || !a.leaf || a.ring_len < 1 || a.first < 0 || a.first >= a.ring_len)
+        return hipErrorInvalidValue;
     if (a.slot_words == 0) return hipSuccess;
     const int block = 256;
     const int64_t grid = (a.slot_words + block - 1) / block;
@@ -346,6 +362,7 @@ hipError_t launch_merge(const MergeArgs &a, hipStream_t stream) {
 
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream) {
     if (n == 0) return hipSuccess;
+    if (!p || n < 0) return hipErrorInvalidValue;
     const int block = 256;
     const int64_t want = (n + block - 1) / block;
     const int grid = (int)(want < 8192 ? want : 8192);

@@ -1,0 +1,14 @@
+"""Host-only checks of the GPU library's index arithmetic (no GPU needed)."""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_fastdiv_and_key_permutation(tmp_path):
+    exe = str(tmp_path / "layout_check")
+    subprocess.run(["/opt/rocm/bin/hipcc", "-O2", "-std=c++17", "-x", "hip", "--offload-arch=gfx950",
+                    os.path.join(HERE, "host", "layout_check.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
