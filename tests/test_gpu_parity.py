@@ -105,7 +105,7 @@ def test_widths_and_padding(env, W):
 def test_thresholds(env, num, den):
     rng = np.random.default_rng(num * 100 + den)
     W, H = 96, 12
-    frames = brute.tiny_frames(rng, 14, W, H, n_colours=24)
+    frames = brute.tiny_frames(rng, 14, W, H, n_colours=24, row_pitch=288)
     check_against_oracle(env, W, H, 3, frames, 10, num, den, label="thr")
 
 
@@ -113,7 +113,7 @@ def test_thresholds(env, num, den):
 def test_regions(env, rw, rh, d):
     rng = np.random.default_rng(rw * rh + d)
     W, H = 200, 70
-    frames = brute.tiny_frames(rng, 6, W, H, n_colours=12)
+    frames = brute.tiny_frames(rng, 6, W, H, n_colours=12, row_pitch=608)
     check_against_oracle(env, W, H, d, frames, 4, 1, 2, rw=rw, rh=rh, label="region",
                          counts=(d <= 6))
 
@@ -186,7 +186,7 @@ def test_repeat_runs_identical(env):
     obg, O = env
     rng = np.random.default_rng(99)
     W, H = 480, 270
-    frames = brute.tiny_frames(rng, 8, W, H, n_colours=40)
+    frames = brute.tiny_frames(rng, 8, W, H, n_colours=40, row_pitch=1440)
     for d, rw, rh in [(4, 0, 0), (5, 0, 0), (6, 0, 0), (4, 32, 32)]:
         g = obg.FrameGeom(W, H, d, region_w=rw, region_h=rh)
         dev = upload(frames, g.frame_pitch)
