@@ -127,6 +127,29 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
                  const uint32_t *leafset, uint64_t *mask, uint32_t *occ_out,
                  hipStream_t stream);
 
+/*
+ * Launch-shape knobs of the pixel kernels, process-wide, for the autotuner
+ * (0 restores the built-in default).  They change speed only: every setting
+ * gives the same bytes.
+ *   OBG_TUNE_TRAIN_BLOCK        threads per workgroup of occupancy-only
+ *                               passes: 256 or 1024 (default 1024)
+ *   OBG_TUNE_OCC_BLIND          1 = set occupancy bits with an unconditional
+ *                               LDS atomic OR, 2 = test the bit first (default)
+ *   OBG_TUNE_OCC_WG_PER_CU      workgroups per CU of passes that build
+ *                               occupancy (default 2 at 1024 threads, else 4)
+ *   OBG_TUNE_CLASSIFY_WG_PER_CU workgroups per CU of classify-only passes
+ *                               (default: as many as LDS and waves allow)
+ *   OBG_TUNE_CLASSIFY_SPAN      16-pixel groups per work item (default 4096)
+ */
+#define OBG_TUNE_TRAIN_BLOCK         0
+#define OBG_TUNE_OCC_BLIND           1
+#define OBG_TUNE_OCC_WG_PER_CU       2
+#define OBG_TUNE_CLASSIFY_WG_PER_CU  3
+#define OBG_TUNE_CLASSIFY_SPAN       4
+#define OBG_TUNE_COUNT               5
+int obg_tune_set(int key, int value);
+int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
+
 /* Message of the calling thread's last failed call ("" if none). */
 const char *obg_last_error(void);
 

@@ -58,6 +58,8 @@ int check_geom(const obg_geom *g, Geo *o, bool pixels) {
     o->words = leaf_words(g->depth);
     o->mask_row_words = (g->width + 63) / 64;
     if (pixels) {
+        if (g->frame_pitch > 0x7FFFFFFFLL)
+            return fail(OBG_EINVAL, "frame_pitch must be below 2 GiB");
         if (g->row_pitch < 3 * (int64_t)g->width)
             return fail(OBG_EINVAL, "row_pitch %lld < 3*width %lld", (long long)g->row_pitch, 3LL * g->width);
         if (g->frame_pitch < (int64_t)g->height * g->row_pitch)
@@ -83,6 +85,15 @@ int cu_count() {
 }
 
 const size_t kStripLdsMax = 64 * 1024;
+
+// Launch-shape knobs of the pixel kernels (0 = built-in default).
+int g_tune[OBG_TUNE_COUNT] = {0};
+std::mutex g_tune_mu;
+
+int tune(int key, int dflt) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune[key] ? g_tune[key] : dflt;
+}
 
 // Does the LDS strip kernel handle this geometry and mode?
 bool strip_ok(const Geo &g, int mode) {
@@ -142,26 +153,37 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.div_tile = make_fastdiv(g.region_w ? (uint32_t)(g.region_w / 16) : (uint32_t)a.gpr);
     const int64_t groups_strip = (int64_t)a.strip_rows * a.gpr;
     if (groups_strip > (1LL << 30)) return fail(OBG_EINVAL, "frame too large");
-    const int block = 256;
+    const bool occ_only = (mode & MODE_MASK) == 0;
+    const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024) : 256;
+    const bool blind = (mode & MODE_OCC) ? tune(OBG_TUNE_OCC_BLIND, 2) == 1 : false;
+    if (block != 256 && block != 1024) return fail(OBG_EINVAL, "train block size must be 256 or 1024");
     const size_t lds = (size_t)g.reg_cols * g.words * 4 *
                        (((mode & MODE_MASK) ? 1 : 0) + ((mode & MODE_OCC) ? 1 : 0));
     const int cus = cu_count();
-    int per_cu = lds ? (int)((160 * 1024) / lds) : 8;
-    if (per_cu > 8) per_cu = 8;
+    // workgroups per CU: LDS and the 32 waves of a CU bound it
+    int per_cu = lds ? (int)((160 * 1024) / lds) : 32;
+    const int wave_cap = 32 / (block / 64);
+    if (per_cu > wave_cap) per_cu = wave_cap;
     if (per_cu < 1) per_cu = 1;
     const int64_t n_sf = (int64_t)a.n_strips * n_frames;
     int64_t spans;
-    int64_t target = (int64_t)cus * per_cu;
+    int64_t target;
     if (mode & MODE_OCC) {
-        // fewer, larger items: each (frame, strip) segment costs one flush
-        int64_t t2 = (int64_t)cus * (per_cu < 2 ? per_cu : 2);
-        spans = (t2 + n_sf - 1) / n_sf;
+        // each (frame, strip) segment of a workgroup costs one LDS flush:
+        // few, large items
+        int want = tune(OBG_TUNE_OCC_WG_PER_CU, block == 1024 ? 2 : 4);
+        if (want > per_cu) want = per_cu;
+        target = (int64_t)cus * want;
+        spans = (target + n_sf - 1) / n_sf;
         const int64_t cap = (groups_strip + block - 1) / block;
         if (spans > cap) spans = cap;
         if (spans < 1) spans = 1;
-        target = t2;
     } else {
-        spans = (groups_strip + 2047) / 2048;
+        int want = tune(OBG_TUNE_CLASSIFY_WG_PER_CU, per_cu);
+        if (want > per_cu) want = per_cu;
+        target = (int64_t)cus * want;
+        const int64_t span_groups = tune(OBG_TUNE_CLASSIFY_SPAN, 4096);
+        spans = (groups_strip + span_groups - 1) / span_groups;
     }
     const int64_t span = (groups_strip + spans - 1) / spans;
     const int64_t n_items = n_sf * spans;
@@ -175,7 +197,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.occ = occ;
     a.counts = counts;
     const int grid = (int)(n_items < target ? n_items : target);
-    if ((e = launch_strip(g.depth, mode, a, grid, block, lds, st)) != hipSuccess)
+    if ((e = launch_strip(g.depth, mode, a, grid, block, blind, lds, st)) != hipSuccess)
         return hip_fail(e, "strip kernel launch");
     return OBG_OK;
 }
@@ -257,6 +279,20 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, const 
     if ((uintptr_t)rgb % 16) return fail(OBG_EALIGN, "rgb must be 16-byte aligned");
     const int mode = MODE_MASK | (occ_out ? MODE_OCC : 0);
     return run_pixels(o, mode, rgb, n_frames, leafset, mask, occ_out, nullptr, stream);
+}
+
+int obg_tune_set(int key, int value) {
+    if (key < 0 || key >= OBG_TUNE_COUNT) return fail(OBG_EINVAL, "unknown tuning key %d", key);
+    if (value < 0) return fail(OBG_EINVAL, "tuning value must be >= 0");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = value;
+    return OBG_OK;
+}
+
+int obg_tune_get(int key) {
+    if (key < 0 || key >= OBG_TUNE_COUNT) return -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune[key];
 }
 
 const char *obg_last_error(void) { return g_err.c_str(); }

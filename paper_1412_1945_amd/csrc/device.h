@@ -86,12 +86,4 @@ __device__ __forceinline__ uint32_t path_key(uint32_t r, uint32_t g, uint32_t b,
     return k;
 }
 
-__device__ __forceinline__ void load48(const uint8_t *p, uint32_t (&u)[12]) {
-    const uint4 *q = reinterpret_cast<const uint4 *>(p);
-    const uint4 a = q[0], b = q[1], c = q[2];
-    u[0] = a.x; u[1] = a.y; u[2] = a.z; u[3] = a.w;
-    u[4] = b.x; u[5] = b.y; u[6] = b.z; u[7] = b.w;
-    u[8] = c.x; u[9] = c.y; u[10] = c.z; u[11] = c.w;
-}
-
 }  // namespace obg

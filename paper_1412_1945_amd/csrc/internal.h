@@ -58,7 +58,7 @@ struct MergeArgs {
 
 enum StripMode { MODE_MASK = 1, MODE_OCC = 2, MODE_COUNTS = 4 };
 
-hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block,
+hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block, bool blind,
                         size_t lds_bytes, hipStream_t stream);
 hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t stream);

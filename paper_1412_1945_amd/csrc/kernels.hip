@@ -74,8 +74,33 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
 
 // ---------------------------------------------------------------------------
 // Per-group work
+//
+// Frames are read through a buffer resource per (frame, strip): offsets are
+// 32-bit and a read past the end of the frame returns zeros instead of
+// faulting, so the partial group at the end of a row and the padding groups
+// that only write zero mask bits need no separate load path.
 
-template <int D, int MODE, bool FULL>
+typedef __attribute__((ext_vector_type(4))) unsigned int v4u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Issue the three 16-byte loads of group g (16 pixels = 48 bytes).
+__device__ __forceinline__ void fetch_group(__amdgpu_buffer_rsrc_t rs, const StripArgs &a, int g,
+                                            uint32_t (&u)[12], uint32_t &yr, uint32_t &gx) {
+    yr = fdiv((uint32_t)g, a.div_gpr);
+    gx = (uint32_t)g - yr * (uint32_t)a.gpr;
+    const uint32_t off = yr * (uint32_t)a.row_pitch + 48u * gx;
+    const v4u v0 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    const v4u v1 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+    const v4u v2 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 32, 0, 0));
+    u[0] = v0.x; u[1] = v0.y; u[2] = v0.z; u[3] = v0.w;
+    u[4] = v1.x; u[5] = v1.y; u[6] = v1.z; u[7] = v1.w;
+    u[8] = v2.x; u[9] = v2.y; u[10] = v2.z; u[11] = v2.w;
+}
+
+template <int D, int MODE, bool BLIND, bool GUARD>
 __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nvalid,
                                                  const uint32_t *leaf_tile, uint32_t *occ_tile,
                                                  uint32_t *__restrict__ cnt) {
@@ -86,13 +111,18 @@ __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nv
     uint32_t run_j = 0xFFFFFFFFu, run_n = 0;
 #pragma unroll
     for (int p = 0; p < 16; ++p) {
-        if (FULL || p < nvalid) {
-            const uint32_t j = concat_index<D>(u, p);
-            if (MASK) present |= ((leaf_tile[j >> 5] >> (j & 31)) & 1u) << p;
+        const uint32_t j = concat_index<D>(u, p);
+        // mask bits of pixels past the row end are cleared by the caller
+        if (MASK) present |= ((leaf_tile[j >> 5] >> (j & 31)) & 1u) << p;
+        if ((OCC || CNT) && (!GUARD || p < nvalid)) {
             if (OCC) {
                 uint32_t *w = &occ_tile[j >> 5];
                 const uint32_t m = 1u << (j & 31);
-                if ((*w & m) == 0) atomicOr(w, m);
+                if (BLIND) {
+                    atomicOr(w, m);
+                } else if ((*w & m) == 0) {
+                    atomicOr(w, m);
+                }
             }
             if (CNT) {
                 if (j == run_j) {
@@ -109,15 +139,46 @@ __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nv
     return present;
 }
 
-template <int D, int MODE>
-__global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
+template <int D, int MODE, bool BLIND>
+__device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffer_rsrc_t ms,
+                                              const uint32_t (&u)[12], uint32_t yr, uint32_t gx,
+                                              const uint32_t *leaf_lds, uint32_t *occ_lds,
+                                              uint32_t *__restrict__ cbase) {
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
+    constexpr int WORDS = leaf_words(D);
+    constexpr int LC = leaf_count(D);
+    int nv = a.width - (int)gx * 16;
+    nv = nv < 0 ? 0 : (nv > 16 ? 16 : nv);
+    int c = 0;
+    if (a.reg_cols > 1) {
+        c = (int)fdiv(gx, a.div_tile);
+        c = c < a.reg_cols ? c : a.reg_cols - 1;     // padding groups: result discarded
+    }
+    const uint32_t *leaf_tile = leaf_lds + c * WORDS;
+    uint32_t *occ_tile = occ_lds + c * WORDS;
+    uint32_t *cnt = CNT ? cbase + (int64_t)c * LC : nullptr;
+    uint32_t present;
+    if (nv == 16)
+        present = group_pixels<D, MODE, BLIND, false>(u, 16, leaf_tile, occ_tile, cnt);
+    else
+        present = group_pixels<D, MODE, BLIND, true>(u, nv, leaf_tile, occ_tile, cnt);
+    if (MASK) {
+        const uint32_t valid = 0xFFFFu >> (16 - nv);
+        const uint32_t off = yr * (uint32_t)a.mask_row_words * 8u + 2u * gx;
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(~present & valid), ms, off, 0, 0);
+    }
+}
+
+template <int D, int MODE, int BLOCK, bool BLIND>
+__global__ __launch_bounds__(BLOCK) void strip_kernel(StripArgs a) {
     extern __shared__ uint32_t lds[];
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
     constexpr int WORDS = leaf_words(D);
     constexpr int LC = leaf_count(D);
-    const int tid = threadIdx.x, nt = blockDim.x;
+    const int tid = threadIdx.x;
     const int strip_words = a.reg_cols * WORDS;
     uint32_t *leaf_lds = lds;
     uint32_t *occ_lds = lds + (MASK ? strip_words : 0);
@@ -135,15 +196,15 @@ __global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
             __syncthreads();
             occ_from_lds<D>(occ_lds,
                             a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * a.reg_cols) * WORDS,
-                            strip_words, tid, nt);
+                            strip_words, tid, BLOCK);
         }
         if (MASK && s != cur_s) {
             __syncthreads();
-            leaf_to_lds<D>(a.leaf + (int64_t)s * a.reg_cols * WORDS, leaf_lds, strip_words, tid, nt);
+            leaf_to_lds<D>(a.leaf + (int64_t)s * a.reg_cols * WORDS, leaf_lds, strip_words, tid, BLOCK);
         }
         if (OCC && new_seg) {
             __syncthreads();
-            for (int i = tid; i < strip_words; i += nt) occ_lds[i] = 0;
+            for (int i = tid; i < strip_words; i += BLOCK) occ_lds[i] = 0;
             __syncthreads();
         }
         cur_s = s;
@@ -154,54 +215,34 @@ __global__ __launch_bounds__(256) void strip_kernel(StripArgs a) {
         const int gcount = rows * a.gpr;
         const int gb = t * a.span;
         const int ge = min(gb + a.span, gcount);
-        const uint8_t *fbase = a.rgb + (int64_t)f * a.frame_pitch + (int64_t)row0 * a.row_pitch;
-        uint8_t *mbase = MASK ? reinterpret_cast<uint8_t *>(
-                                    a.mask + ((int64_t)f * a.height + row0) * a.mask_row_words)
-                              : nullptr;
+        const int64_t strip_off = (int64_t)row0 * a.row_pitch;
+        const __amdgpu_buffer_rsrc_t rs =
+            make_rsrc(a.rgb + (int64_t)f * a.frame_pitch + strip_off, (uint32_t)(a.frame_pitch - strip_off));
+        __amdgpu_buffer_rsrc_t ms = make_rsrc(nullptr, 0);
+        if (MASK)
+            ms = make_rsrc(a.mask + ((int64_t)f * a.height + row0) * a.mask_row_words,
+                           (uint32_t)rows * (uint32_t)a.mask_row_words * 8u);
         uint32_t *cbase = CNT ? a.counts + ((int64_t)f * a.n_regions + (int64_t)s * a.reg_cols) * LC
                               : nullptr;
-        for (int g = gb + tid; g < ge; g += nt) {
-            const uint32_t yr = fdiv((uint32_t)g, a.div_gpr);
-            const uint32_t gx = (uint32_t)g - yr * (uint32_t)a.gpr;
-            const int x0 = (int)gx * 16;
-            const uint8_t *src = fbase + (int64_t)yr * a.row_pitch + 48 * (int64_t)gx;
-            uint32_t present = 0, valid = 0;
-            if (x0 < a.width) {
-                const int c = (int)fdiv(gx, a.div_tile);
-                const uint32_t *leaf_tile = leaf_lds + c * WORDS;
-                uint32_t *occ_tile = occ_lds + c * WORDS;
-                uint32_t *cnt = CNT ? cbase + (int64_t)c * LC : nullptr;
-                uint32_t u[12];
-                if (x0 + 16 <= a.width) {
-                    load48(src, u);
-                    present = group_pixels<D, MODE, true>(u, 16, leaf_tile, occ_tile, cnt);
-                    valid = 0xFFFFu;
-                } else {
-                    const int nv = a.width - x0;
-                    const int chunks = (3 * nv + 15) / 16;
-                    const uint4 *q = reinterpret_cast<const uint4 *>(src);
-#pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        uint4 v = make_uint4(0, 0, 0, 0);
-                        if (k < chunks) v = q[k];
-                        u[4 * k + 0] = v.x; u[4 * k + 1] = v.y;
-                        u[4 * k + 2] = v.z; u[4 * k + 3] = v.w;
-                    }
-                    present = group_pixels<D, MODE, false>(u, nv, leaf_tile, occ_tile, cnt);
-                    valid = (1u << nv) - 1u;
-                }
-            }
-            if (MASK) {
-                *reinterpret_cast<uint16_t *>(mbase + (int64_t)yr * a.mask_row_words * 8 + 2 * (int64_t)gx) =
-                    (uint16_t)(~present & valid);
-            }
+        // two groups in flight per lane: the loads of the next group are
+        // issued before the current one is worked on
+        uint32_t ua[12], ub[12], ya = 0, xa = 0, yb = 0, xb = 0;
+        int g = gb + tid;
+        if (g < ge) fetch_group(rs, a, g, ua, ya, xa);
+        for (; g < ge; g += 2 * BLOCK) {
+            const int g1 = g + BLOCK;
+            if (g1 < ge) fetch_group(rs, a, g1, ub, yb, xb);
+            consume_group<D, MODE, BLIND>(a, ms, ua, ya, xa, leaf_lds, occ_lds, cbase);
+            const int g2 = g + 2 * BLOCK;
+            if (g2 < ge) fetch_group(rs, a, g2, ua, ya, xa);
+            if (g1 < ge) consume_group<D, MODE, BLIND>(a, ms, ub, yb, xb, leaf_lds, occ_lds, cbase);
         }
     }
     if (OCC && cur_f >= 0) {
         __syncthreads();
         occ_from_lds<D>(occ_lds,
                         a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * a.reg_cols) * WORDS,
-                        strip_words, tid, nt);
+                        strip_words, tid, BLOCK);
     }
 }
 
@@ -254,18 +295,33 @@ __global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
     uint32_t c[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b) c[b] = 0;
+    // eight window slots per round: their loads are independent and in flight together
     int slot = a.first;
-    for (int t = 0; t < a.n_trees; ++t) {
-        uint32_t carry = a.occ_ring[(int64_t)slot * a.slot_words + i] & valid;
+    for (int t0 = 0; t0 < a.n_trees; t0 += 8) {
+        uint32_t x[8];
 #pragma unroll
-        for (int b = 0; b < 16; ++b) {
-            if (b < a.planes) {
-                const uint32_t tmp = c[b] & carry;
-                c[b] ^= carry;
-                carry = tmp;
+        for (int k = 0; k < 8; ++k) {
+            x[k] = 0;
+            if (t0 + k < a.n_trees) {
+                int sl = slot + k;
+                if (sl >= a.ring_len) sl -= a.ring_len;
+                x[k] = a.occ_ring[(int64_t)sl * a.slot_words + i] & valid;
             }
         }
-        if (++slot == a.ring_len) slot = 0;
+        slot += 8;
+        while (slot >= a.ring_len) slot -= a.ring_len;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint32_t carry = x[k];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                if (b < a.planes) {
+                    const uint32_t tmp = c[b] & carry;
+                    c[b] ^= carry;
+                    carry = tmp;
+                }
+            }
+        }
     }
     // bit-sliced count >= kmin
     uint32_t ge = 0, eq = 0xFFFFFFFFu;
@@ -291,26 +347,35 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
 // ---------------------------------------------------------------------------
 // Launchers
 
+template <int D, int MODE>
+static hipError_t launch_mode(int block, bool blind, const StripArgs &a, int grid, size_t lds,
+                              hipStream_t st) {
+    if (block == 256 && !blind)
+        hipLaunchKernelGGL((strip_kernel<D, MODE, 256, false>), dim3(grid), dim3(256), lds, st, a);
+    else if (block == 256)
+        hipLaunchKernelGGL((strip_kernel<D, MODE, 256, true>), dim3(grid), dim3(256), lds, st, a);
+    else if (block == 1024 && !blind)
+        hipLaunchKernelGGL((strip_kernel<D, MODE, 1024, false>), dim3(grid), dim3(1024), lds, st, a);
+    else if (block == 1024)
+        hipLaunchKernelGGL((strip_kernel<D, MODE, 1024, true>), dim3(grid), dim3(1024), lds, st, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <int D>
-static hipError_t launch_strip_d(int mode, const StripArgs &a, int grid, int block, size_t lds,
-                                 hipStream_t st) {
+static hipError_t launch_strip_d(int mode, int block, bool blind, const StripArgs &a, int grid,
+                                 size_t lds, hipStream_t st) {
     switch (mode) {
         case MODE_MASK:
-            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK>), dim3(grid), dim3(block), lds, st, a);
-            break;
-        case MODE_OCC:
-            hipLaunchKernelGGL((strip_kernel<D, MODE_OCC>), dim3(grid), dim3(block), lds, st, a);
-            break;
-        case MODE_MASK | MODE_OCC:
-            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK | MODE_OCC>), dim3(grid), dim3(block), lds, st, a);
-            break;
-        case MODE_OCC | MODE_COUNTS:
-            hipLaunchKernelGGL((strip_kernel<D, MODE_OCC | MODE_COUNTS>), dim3(grid), dim3(block), lds, st, a);
-            break;
-        default:
-            return hipErrorInvalidValue;
+            if (block != 256) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK, 256, false>), dim3(grid), dim3(256), lds, st, a);
+            return hipGetLastError();
+        case MODE_OCC: return launch_mode<D, MODE_OCC>(block, blind, a, grid, lds, st);
+        case MODE_MASK | MODE_OCC: return launch_mode<D, MODE_MASK | MODE_OCC>(block, blind, a, grid, lds, st);
+        case MODE_OCC | MODE_COUNTS: return launch_mode<D, MODE_OCC | MODE_COUNTS>(block, blind, a, grid, lds, st);
+        default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 // Every pointer a mode writes or reads must be set; a launch with a missing
@@ -323,16 +388,17 @@ static bool strip_pointers_ok(int mode, const StripArgs &a) {
     return true;
 }
 
-hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block,
+hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block, bool blind,
                         size_t lds_bytes, hipStream_t stream) {
-    if (!strip_pointers_ok(mode, a) || grid < 1 || block != 256) return hipErrorInvalidValue;
+    if (!strip_pointers_ok(mode, a) || grid < 1) return hipErrorInvalidValue;
+    if (a.frame_pitch > 0x7FFFFFFFLL) return hipErrorInvalidValue;
     switch (depth) {
-        case 1: return launch_strip_d<1>(mode, a, grid, block, lds_bytes, stream);
-        case 2: return launch_strip_d<2>(mode, a, grid, block, lds_bytes, stream);
-        case 3: return launch_strip_d<3>(mode, a, grid, block, lds_bytes, stream);
-        case 4: return launch_strip_d<4>(mode, a, grid, block, lds_bytes, stream);
-        case 5: return launch_strip_d<5>(mode, a, grid, block, lds_bytes, stream);
-        case 6: return launch_strip_d<6>(mode, a, grid, block, lds_bytes, stream);
+        case 1: return launch_strip_d<1>(mode, block, blind, a, grid, lds_bytes, stream);
+        case 2: return launch_strip_d<2>(mode, block, blind, a, grid, lds_bytes, stream);
+        case 3: return launch_strip_d<3>(mode, block, blind, a, grid, lds_bytes, stream);
+        case 4: return launch_strip_d<4>(mode, block, blind, a, grid, lds_bytes, stream);
+        case 5: return launch_strip_d<5>(mode, block, blind, a, grid, lds_bytes, stream);
+        case 6: return launch_strip_d<6>(mode, block, blind, a, grid, lds_bytes, stream);
         default: return hipErrorInvalidValue;
     }
 }

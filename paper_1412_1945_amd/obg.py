@@ -54,6 +54,8 @@ def load() -> ctypes.CDLL:
             "obg_train_frame": (ctypes.c_int, [G, P, I32, P, P, P]),
             "obg_merge": (ctypes.c_int, [G, P, I32, I32, I32, U32, U32, P, P]),
             "obg_classify": (ctypes.c_int, [G, P, I32, P, P, P, P]),
+            "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+            "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
             "obg_last_error": (ctypes.c_char_p, []),
             "obg_version": (ctypes.c_char_p, []),
         }
@@ -67,7 +69,8 @@ def load() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
-            "obg_merge", "obg_classify", "obg_last_error", "obg_version"]
+            "obg_merge", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_last_error",
+            "obg_version"]
 
 
 @dataclass
@@ -176,6 +179,20 @@ def obg_classify(g: FrameGeom, rgb: torch.Tensor, n_frames: int, leafset: torch.
         _need(occ_out, torch.int32, n_frames * g.n_regions * g.words, "occ_out")
     _check(load().obg_classify(ctypes.byref(g.c()), _ptr(rgb), n_frames, _ptr(leafset),
                                _ptr(mask), _ptr(occ_out), _stream(stream)))
+
+
+TUNE_KEYS = {"train_block": 0, "occ_blind": 1, "occ_wg_per_cu": 2,
+             "classify_wg_per_cu": 3, "classify_span": 4}
+
+
+def obg_tune_set(key, value: int):
+    k = TUNE_KEYS[key] if isinstance(key, str) else key
+    _check(load().obg_tune_set(k, value))
+
+
+def obg_tune_get(key) -> int:
+    k = TUNE_KEYS[key] if isinstance(key, str) else key
+    return load().obg_tune_get(k)
 
 
 def obg_version() -> str:
