@@ -133,20 +133,27 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
  * gives the same bytes.
  *   OBG_TUNE_TRAIN_BLOCK        threads per workgroup of occupancy-only
  *                               passes: 256 or 1024 (default 1024)
- *   OBG_TUNE_OCC_BLIND          1 = set occupancy bits with an unconditional
- *                               LDS atomic OR, 2 = test the bit first (default)
+ *   OBG_TUNE_OCC_BLIND          reserved (occupancy bits are set with an
+ *                               unconditional LDS atomic OR)
  *   OBG_TUNE_OCC_WG_PER_CU      workgroups per CU of passes that build
  *                               occupancy (default 2 at 1024 threads, else 4)
  *   OBG_TUNE_CLASSIFY_WG_PER_CU workgroups per CU of classify-only passes
  *                               (default: as many as LDS and waves allow)
  *   OBG_TUNE_CLASSIFY_SPAN      16-pixel groups per work item (default 4096)
+ *   OBG_TUNE_CLASSIFY_BLOCK     threads per workgroup of classify-only
+ *                               passes: 256 (default) or 512
+ *   OBG_TUNE_LAYOUT             LDS order of d <= 5 trees: 1 = wide table
+ *                               indexed by the pixel's R,G bytes (default),
+ *                               2 = compact
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1
 #define OBG_TUNE_OCC_WG_PER_CU       2
 #define OBG_TUNE_CLASSIFY_WG_PER_CU  3
 #define OBG_TUNE_CLASSIFY_SPAN       4
-#define OBG_TUNE_COUNT               5
+#define OBG_TUNE_CLASSIFY_BLOCK      5
+#define OBG_TUNE_LAYOUT              6
+#define OBG_TUNE_COUNT               7
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 

@@ -95,13 +95,18 @@ int tune(int key, int dflt) {
     return g_tune[key] ? g_tune[key] : dflt;
 }
 
-// Does the LDS strip kernel handle this geometry and mode?
-bool strip_ok(const Geo &g, int mode) {
+// Does the LDS strip kernel handle this geometry and mode?  Picks the LDS
+// order: the wide one when it fits, else the compact one.
+bool strip_ok(const Geo &g, int mode, int *lay) {
     if (g.depth > 6) return false;
     if (g.region_w && (g.region_w % 16) != 0) return false;
-    const size_t tiles = (size_t)g.reg_cols * g.words * 4;
-    const size_t lds = tiles * (((mode & MODE_MASK) ? 1 : 0) + ((mode & MODE_OCC) ? 1 : 0));
-    return lds <= kStripLdsMax;
+    const size_t wide = strip_lds_bytes(g.depth, mode, g.reg_cols, LAY_WIDE);
+    if (wide && wide <= kStripLdsMax && tune(OBG_TUNE_LAYOUT, 1) == 1) {
+        *lay = LAY_WIDE;
+        return true;
+    }
+    *lay = LAY_COMPACT;
+    return strip_lds_bytes(g.depth, mode, g.reg_cols, LAY_COMPACT) <= kStripLdsMax;
 }
 
 int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, const uint32_t *leaf,
@@ -115,7 +120,8 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         const int64_t n = (int64_t)n_frames * g.n_regions * leaf_count(g.depth);
         if ((e = launch_fill_u32(counts, n, 0u, st)) != hipSuccess) return hip_fail(e, "zero counts");
     }
-    if (!strip_ok(g, mode)) {
+    int lay = LAY_COMPACT;
+    if (!strip_ok(g, mode, &lay)) {
         GenericArgs a{};
         a.rgb = rgb;
         a.frame_pitch = g.frame_pitch;
@@ -154,11 +160,15 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     const int64_t groups_strip = (int64_t)a.strip_rows * a.gpr;
     if (groups_strip > (1LL << 30)) return fail(OBG_EINVAL, "frame too large");
     const bool occ_only = (mode & MODE_MASK) == 0;
-    const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024) : 256;
-    const bool blind = (mode & MODE_OCC) ? tune(OBG_TUNE_OCC_BLIND, 2) == 1 : false;
-    if (block != 256 && block != 1024) return fail(OBG_EINVAL, "train block size must be 256 or 1024");
-    const size_t lds = (size_t)g.reg_cols * g.words * 4 *
-                       (((mode & MODE_MASK) ? 1 : 0) + ((mode & MODE_OCC) ? 1 : 0));
+    // classify: large tables leave room for few workgroups per CU; 512-thread
+    // groups keep the CU at its 32 waves with 4 of them
+    const size_t lds_need = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
+    const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024)
+                               : (mode == MODE_MASK ? tune(OBG_TUNE_CLASSIFY_BLOCK, lds_need > 20 * 1024 ? 512 : 256)
+                                                    : 256);
+    if (occ_only && block != 256 && block != 1024) return fail(OBG_EINVAL, "train block size must be 256 or 1024");
+    if (!occ_only && block != 256 && block != 512) return fail(OBG_EINVAL, "classify block size must be 256 or 512");
+    const size_t lds = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
     const int cus = cu_count();
     // workgroups per CU: LDS and the 32 waves of a CU bound it
     int per_cu = lds ? (int)((160 * 1024) / lds) : 32;
@@ -197,7 +207,9 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.occ = occ;
     a.counts = counts;
     const int grid = (int)(n_items < target ? n_items : target);
-    if ((e = launch_strip(g.depth, mode, a, grid, block, blind, lds, st)) != hipSuccess)
+    // one region per strip: the kernel's tables are static, no dynamic LDS
+    const size_t dyn_lds = g.reg_cols > 1 ? lds : 0;
+    if ((e = launch_strip(g.depth, mode, a, grid, block, lay, g.reg_cols > 1, dyn_lds, st)) != hipSuccess)
         return hip_fail(e, "strip kernel launch");
     return OBG_OK;
 }

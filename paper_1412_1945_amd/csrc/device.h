@@ -6,12 +6,18 @@
 //               base-8 digits, c_0 most significant, c_i = 4r_i + 2g_i + b_i
 //               with r_i = bit 7-i of R.  In bits: bit 3m+2 of K is bit m of
 //               R' = R >> (8-d), bit 3m+1 is bit m of G', bit 3m is bit m of B'.
-//   concat J    (LDS only):  J = R' << 2d | G' << d | B'.
+//   LDS index L (on chip): bit (L & 31) of 32-bit LDS word (L >> 5), in one
+//               of two orders:
+//     LAY_COMPACT  L = R' << 2d | G' << d | B'            (8^d bits)
+//     LAY_WIDE     L = G' << 13 | R' << 5 | B'   (d <= 5; a sparse table)
+//               The wide order follows the bytes of a pixel: the LDS byte
+//               address 4 * (G' << 8 | R') is the R,G byte pair of the pixel
+//               shifted and masked in one go, and B' is the bit.
 //
-// J is what a pixel's bytes give with three bit-field extracts and two
-// shift-or operations; K would need a bit interleave per pixel.  Both orders
-// hold the same set (the map between them is a fixed permutation of the 3d
-// index bits), so bitsets are converted when they enter or leave LDS.
+// L comes from a pixel's bytes with a few shifts and masks; K would need a
+// bit interleave per pixel.  The map between K and L permutes index bits
+// (with zero gaps in the wide order), so bitsets are converted when they
+// enter or leave LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,26 +25,37 @@
 
 namespace obg {
 
+enum { LAY_COMPACT = 0, LAY_WIDE = 1 };
+
 __host__ __device__ constexpr int leaf_count(int d) { return 1 << (3 * d); }
 __host__ __device__ constexpr int leaf_words(int d) { return d >= 2 ? (1 << (3 * d - 5)) : 1; }
 
-// K -> J and J -> K; both are permutations of the index bits.
-__host__ __device__ constexpr uint32_t concat_from_key(uint32_t k, int d) {
-    uint32_t j = 0;
-    for (int m = 0; m < d; ++m) {
-        j |= ((k >> (3 * m + 2)) & 1u) << (2 * d + m);
-        j |= ((k >> (3 * m + 1)) & 1u) << (d + m);
-        j |= ((k >> (3 * m)) & 1u) << m;
-    }
-    return j;
+// 32-bit LDS words of one tree in an LDS order
+__host__ __device__ constexpr int lds_words(int d, int lay) {
+    return lay == LAY_WIDE ? ((((1 << d) - 1) << 8) | ((1 << d) - 1)) + 1
+                           : (d >= 2 ? (1 << (3 * d - 5)) : 1);
 }
 
-__host__ __device__ constexpr uint32_t key_from_concat(uint32_t j, int d) {
+__host__ __device__ constexpr uint32_t lds_from_key(uint32_t k, int d, int lay) {
+    uint32_t r = 0, g = 0, b = 0;
+    for (int m = 0; m < d; ++m) {
+        r |= ((k >> (3 * m + 2)) & 1u) << m;
+        g |= ((k >> (3 * m + 1)) & 1u) << m;
+        b |= ((k >> (3 * m)) & 1u) << m;
+    }
+    return lay == LAY_WIDE ? ((g << 13) | (r << 5) | b) : ((((r << d) | g) << d) | b);
+}
+
+__host__ __device__ constexpr uint32_t key_from_lds(uint32_t l, int d, int lay) {
+    const uint32_t msk = (1u << d) - 1u;
+    const uint32_t b = l & msk;
+    const uint32_t r = lay == LAY_WIDE ? (l >> 5) & msk : (l >> (2 * d)) & msk;
+    const uint32_t g = lay == LAY_WIDE ? (l >> 13) & msk : (l >> d) & msk;
     uint32_t k = 0;
     for (int m = 0; m < d; ++m) {
-        k |= ((j >> (2 * d + m)) & 1u) << (3 * m + 2);
-        k |= ((j >> (d + m)) & 1u) << (3 * m + 1);
-        k |= ((j >> m) & 1u) << (3 * m);
+        k |= ((r >> m) & 1u) << (3 * m + 2);
+        k |= ((g >> m) & 1u) << (3 * m + 1);
+        k |= ((b >> m) & 1u) << (3 * m);
     }
     return k;
 }
@@ -65,15 +82,34 @@ __host__ __device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) 
     return (t + ((n - t) >> f.s1)) >> f.s2;
 }
 
-// Concat index of pixel p (0..15) of a 16-pixel group held as 12 dwords.
-template <int D>
-__device__ __forceinline__ uint32_t concat_index(const uint32_t (&u)[12], int p) {
+// LDS byte address (within one tree's table) and bit of pixel p (0..15) of a
+// 16-pixel group held as 12 dwords.  Only the low 5 bits of `bit` count.
+template <int D, int LAY>
+__device__ __forceinline__ void lds_pos(const uint32_t (&u)[12], int p, uint32_t &addr, uint32_t &bit) {
     constexpr int S = 8 - D;
-    const int br = 3 * p, bg = 3 * p + 1, bb = 3 * p + 2;
-    const uint32_t R = __builtin_amdgcn_ubfe(u[br >> 2], (br & 3) * 8 + S, D);
-    const uint32_t G = __builtin_amdgcn_ubfe(u[bg >> 2], (bg & 3) * 8 + S, D);
-    const uint32_t B = __builtin_amdgcn_ubfe(u[bb >> 2], (bb & 3) * 8 + S, D);
-    return (R << (2 * D)) | (G << D) | B;
+    const int br = 3 * p, bb = 3 * p + 2;
+    if (LAY == LAY_WIDE) {
+        static_assert(LAY != LAY_WIDE || D <= 5, "wide order needs d <= 5");
+        // R byte then G byte, shifted so that R' lands at bit 2 and G' at bit 10
+        const int k = br >> 2, o = br & 3;
+        uint32_t rg;
+        if (o < 3)
+            rg = u[k] >> (8 * o + 6 - D);
+        else
+            rg = __builtin_amdgcn_alignbit(u[k + 1], u[k], 30 - D);
+        constexpr uint32_t M = (((1u << D) - 1u) << 2) | (((1u << D) - 1u) << 10);
+        addr = rg & M;
+        bit = (D == 5) ? (u[bb >> 2] >> ((bb & 3) * 8 + S))
+                       : __builtin_amdgcn_ubfe(u[bb >> 2], (bb & 3) * 8 + S, D);
+    } else {
+        const int bg = 3 * p + 1;
+        const uint32_t R = __builtin_amdgcn_ubfe(u[br >> 2], (br & 3) * 8 + S, D);
+        const uint32_t G = __builtin_amdgcn_ubfe(u[bg >> 2], (bg & 3) * 8 + S, D);
+        const uint32_t B = __builtin_amdgcn_ubfe(u[bb >> 2], (bb & 3) * 8 + S, D);
+        const uint32_t l = (((R << D) | G) << D) | B;
+        addr = (l >> 5) << 2;
+        bit = l;
+    }
 }
 
 // Path key of one pixel from its bytes (generic kernels).

@@ -58,8 +58,12 @@ struct MergeArgs {
 
 enum StripMode { MODE_MASK = 1, MODE_OCC = 2, MODE_COUNTS = 4 };
 
-hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block, bool blind,
-                        size_t lds_bytes, hipStream_t stream);
+// lay: LDS order (LAY_WIDE / LAY_COMPACT, see device.h); region: more than
+// one region per strip
+hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block, int lay,
+                        bool region, size_t lds_bytes, hipStream_t stream);
+// LDS bytes one workgroup of the strip kernel needs (0 = order not possible)
+size_t strip_lds_bytes(int depth, int mode, int reg_cols, int lay);
 hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);

@@ -22,51 +22,55 @@
 namespace obg {
 
 // ---------------------------------------------------------------------------
-// LDS <-> HBM bitset conversion (key order in HBM, concat order in LDS)
+// LDS <-> HBM bitset conversion (key order in HBM, LDS order on chip)
 
-template <int D>
+// The bits of one key-order word kw are keys 32*kw + b; their LDS indices are
+// lds_from_key(32*kw) | lds_from_key(b) because the map permutes index bits.
+template <int D, int PAD>
 __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, uint32_t *lds,
-                                            int n_words, int tid, int nt) {
-    constexpr int WORDS = leaf_words(D);
+                                            int n_tiles, int tid, int nt) {
+    constexpr int KW = leaf_words(D);
+    constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
-    for (int i = tid; i < n_words; i += nt) lds[i] = 0;
+    for (int i = tid; i < n_tiles * LW; i += nt) lds[i] = 0;
     __syncthreads();
-    for (int i = tid; i < n_words; i += nt) {
-        const int c = i / WORDS;
-        const int kw = i - c * WORDS;
+    for (int i = tid; i < n_tiles * KW; i += nt) {
+        const int c = i / KW;
+        const int kw = i - c * KW;
         uint32_t bits = leaf[i];
         if (LC < 32) bits &= (1u << (LC & 31)) - 1u;
         if (bits == 0) continue;
-        const uint32_t jbase = concat_from_key((uint32_t)kw << 5, D);
-        uint32_t *tile = lds + c * WORDS;
+        const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
+        uint32_t *tile = lds + c * LW;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             if ((bits >> b) & 1u) {
-                const uint32_t j = jbase | concat_from_key((uint32_t)b, D);
-                atomicOr(&tile[j >> 5], 1u << (j & 31));
+                const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
+                atomicOr(&tile[l >> 5], 1u << (l & 31));
             }
         }
     }
     __syncthreads();
 }
 
-template <int D>
+template <int D, int PAD>
 __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__restrict__ occ,
-                                             int n_words, int tid, int nt) {
-    constexpr int WORDS = leaf_words(D);
+                                             int n_tiles, int tid, int nt) {
+    constexpr int KW = leaf_words(D);
+    constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
-    for (int i = tid; i < n_words; i += nt) {
-        const int c = i / WORDS;
-        const int kw = i - c * WORDS;
-        const uint32_t jbase = concat_from_key((uint32_t)kw << 5, D);
-        const uint32_t *tile = lds + c * WORDS;
+    for (int i = tid; i < n_tiles * KW; i += nt) {
+        const int c = i / KW;
+        const int kw = i - c * KW;
+        const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
+        const uint32_t *tile = lds + c * LW;
         uint32_t out = 0;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const uint32_t j = jbase | concat_from_key((uint32_t)b, D);
-            out |= ((tile[j >> 5] >> (j & 31)) & 1u) << b;
+            const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
+            out |= ((tile[l >> 5] >> (l & 31)) & 1u) << b;
         }
         if (out) atomicOr(&occ[i], out);
     }
@@ -100,7 +104,7 @@ __device__ __forceinline__ void fetch_group(__amdgpu_buffer_rsrc_t rs, const Str
     u[8] = v2.x; u[9] = v2.y; u[10] = v2.z; u[11] = v2.w;
 }
 
-template <int D, int MODE, bool BLIND, bool GUARD>
+template <int D, int MODE, int PAD, bool GUARD>
 __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nvalid,
                                                  const uint32_t *leaf_tile, uint32_t *occ_tile,
                                                  uint32_t *__restrict__ cnt) {
@@ -108,61 +112,60 @@ __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nv
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
     uint32_t present = 0;
-    uint32_t run_j = 0xFFFFFFFFu, run_n = 0;
+    uint32_t run_l = 0xFFFFFFFFu, run_n = 0;
 #pragma unroll
     for (int p = 0; p < 16; ++p) {
-        const uint32_t j = concat_index<D>(u, p);
+        uint32_t addr, bit;
+        lds_pos<D, PAD>(u, p, addr, bit);
         // mask bits of pixels past the row end are cleared by the caller
-        if (MASK) present |= ((leaf_tile[j >> 5] >> (j & 31)) & 1u) << p;
+        if (MASK) {
+            const uint32_t w = *reinterpret_cast<const uint32_t *>(
+                reinterpret_cast<const char *>(leaf_tile) + addr);
+            present |= ((w >> (bit & 31)) & 1u) << p;
+        }
         if ((OCC || CNT) && (!GUARD || p < nvalid)) {
-            if (OCC) {
-                uint32_t *w = &occ_tile[j >> 5];
-                const uint32_t m = 1u << (j & 31);
-                if (BLIND) {
-                    atomicOr(w, m);
-                } else if ((*w & m) == 0) {
-                    atomicOr(w, m);
-                }
-            }
+            if (OCC) atomicOr(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(occ_tile) + addr),
+                              1u << (bit & 31));
             if (CNT) {
-                if (j == run_j) {
+                const uint32_t l = (addr << 3) | (bit & 31);
+                if (l == run_l) {
                     ++run_n;
                 } else {
-                    if (run_n) atomicAdd(&cnt[key_from_concat(run_j, D)], run_n);
-                    run_j = j;
+                    if (run_n) atomicAdd(&cnt[key_from_lds(run_l, D, PAD)], run_n);
+                    run_l = l;
                     run_n = 1;
                 }
             }
         }
     }
-    if (CNT && run_n) atomicAdd(&cnt[key_from_concat(run_j, D)], run_n);
+    if (CNT && run_n) atomicAdd(&cnt[key_from_lds(run_l, D, PAD)], run_n);
     return present;
 }
 
-template <int D, int MODE, bool BLIND>
+template <int D, int MODE, int PAD, bool REGION>
 __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffer_rsrc_t ms,
                                               const uint32_t (&u)[12], uint32_t yr, uint32_t gx,
                                               const uint32_t *leaf_lds, uint32_t *occ_lds,
                                               uint32_t *__restrict__ cbase) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
-    constexpr int WORDS = leaf_words(D);
+    constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
     int nv = a.width - (int)gx * 16;
     nv = nv < 0 ? 0 : (nv > 16 ? 16 : nv);
     int c = 0;
-    if (a.reg_cols > 1) {
+    if (REGION) {
         c = (int)fdiv(gx, a.div_tile);
         c = c < a.reg_cols ? c : a.reg_cols - 1;     // padding groups: result discarded
     }
-    const uint32_t *leaf_tile = leaf_lds + c * WORDS;
-    uint32_t *occ_tile = occ_lds + c * WORDS;
+    const uint32_t *leaf_tile = leaf_lds + c * LW;
+    uint32_t *occ_tile = occ_lds + c * LW;
     uint32_t *cnt = CNT ? cbase + (int64_t)c * LC : nullptr;
     uint32_t present;
     if (nv == 16)
-        present = group_pixels<D, MODE, BLIND, false>(u, 16, leaf_tile, occ_tile, cnt);
+        present = group_pixels<D, MODE, PAD, false>(u, 16, leaf_tile, occ_tile, cnt);
     else
-        present = group_pixels<D, MODE, BLIND, true>(u, nv, leaf_tile, occ_tile, cnt);
+        present = group_pixels<D, MODE, PAD, true>(u, nv, leaf_tile, occ_tile, cnt);
     if (MASK) {
         const uint32_t valid = 0xFFFFu >> (16 - nv);
         const uint32_t off = yr * (uint32_t)a.mask_row_words * 8u + 2u * gx;
@@ -170,18 +173,23 @@ __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffe
     }
 }
 
-template <int D, int MODE, int BLOCK, bool BLIND>
-__global__ __launch_bounds__(BLOCK) void strip_kernel(StripArgs a) {
-    extern __shared__ uint32_t lds[];
+template <int D, int MODE, int BLOCK, int PAD, bool REGION>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((MODE == MODE_MASK && D == 5) ? 8 : 1))) void strip_kernel(StripArgs a) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
-    constexpr int WORDS = leaf_words(D);
+    constexpr int KW = leaf_words(D);
+    constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
+    // one tree per strip: fixed-size tables (their LDS addresses are known
+    // when the kernel is compiled); several: tables sized at launch
+    extern __shared__ uint32_t dyn_lds[];
+    __shared__ uint32_t st_leaf[(!REGION && MASK) ? LW : 1];
+    __shared__ uint32_t st_occ[(!REGION && OCC) ? LW : 1];
     const int tid = threadIdx.x;
-    const int strip_words = a.reg_cols * WORDS;
-    uint32_t *leaf_lds = lds;
-    uint32_t *occ_lds = lds + (MASK ? strip_words : 0);
+    const int tiles = REGION ? a.reg_cols : 1;
+    uint32_t *leaf_lds = REGION ? dyn_lds : st_leaf;
+    uint32_t *occ_lds = REGION ? dyn_lds + (MASK ? tiles * LW : 0) : st_occ;
 
     const int i0 = (int)((int64_t)a.n_items * blockIdx.x / gridDim.x);
     const int i1 = (int)((int64_t)a.n_items * (blockIdx.x + 1) / gridDim.x);
@@ -194,17 +202,17 @@ __global__ __launch_bounds__(BLOCK) void strip_kernel(StripArgs a) {
         const bool new_seg = (s != cur_s) || (f != cur_f);
         if (OCC && new_seg && cur_f >= 0) {
             __syncthreads();
-            occ_from_lds<D>(occ_lds,
-                            a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * a.reg_cols) * WORDS,
-                            strip_words, tid, BLOCK);
+            occ_from_lds<D, PAD>(occ_lds,
+                                 a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * tiles) * KW,
+                                 tiles, tid, BLOCK);
         }
         if (MASK && s != cur_s) {
             __syncthreads();
-            leaf_to_lds<D>(a.leaf + (int64_t)s * a.reg_cols * WORDS, leaf_lds, strip_words, tid, BLOCK);
+            leaf_to_lds<D, PAD>(a.leaf + (int64_t)s * tiles * KW, leaf_lds, tiles, tid, BLOCK);
         }
         if (OCC && new_seg) {
             __syncthreads();
-            for (int i = tid; i < strip_words; i += BLOCK) occ_lds[i] = 0;
+            for (int i = tid; i < tiles * LW; i += BLOCK) occ_lds[i] = 0;
             __syncthreads();
         }
         cur_s = s;
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(BLOCK) void strip_kernel(StripArgs a) {
         if (MASK)
             ms = make_rsrc(a.mask + ((int64_t)f * a.height + row0) * a.mask_row_words,
                            (uint32_t)rows * (uint32_t)a.mask_row_words * 8u);
-        uint32_t *cbase = CNT ? a.counts + ((int64_t)f * a.n_regions + (int64_t)s * a.reg_cols) * LC
+        uint32_t *cbase = CNT ? a.counts + ((int64_t)f * a.n_regions + (int64_t)s * tiles) * LC
                               : nullptr;
         // two groups in flight per lane: the loads of the next group are
         // issued before the current one is worked on
@@ -232,17 +240,17 @@ __global__ __launch_bounds__(BLOCK) void strip_kernel(StripArgs a) {
         for (; g < ge; g += 2 * BLOCK) {
             const int g1 = g + BLOCK;
             if (g1 < ge) fetch_group(rs, a, g1, ub, yb, xb);
-            consume_group<D, MODE, BLIND>(a, ms, ua, ya, xa, leaf_lds, occ_lds, cbase);
+            consume_group<D, MODE, PAD, REGION>(a, ms, ua, ya, xa, leaf_lds, occ_lds, cbase);
             const int g2 = g + 2 * BLOCK;
             if (g2 < ge) fetch_group(rs, a, g2, ua, ya, xa);
-            if (g1 < ge) consume_group<D, MODE, BLIND>(a, ms, ub, yb, xb, leaf_lds, occ_lds, cbase);
+            if (g1 < ge) consume_group<D, MODE, PAD, REGION>(a, ms, ub, yb, xb, leaf_lds, occ_lds, cbase);
         }
     }
     if (OCC && cur_f >= 0) {
         __syncthreads();
-        occ_from_lds<D>(occ_lds,
-                        a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * a.reg_cols) * WORDS,
-                        strip_words, tid, BLOCK);
+        occ_from_lds<D, PAD>(occ_lds,
+                             a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * tiles) * KW,
+                             tiles, tid, BLOCK);
     }
 }
 
@@ -347,35 +355,50 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
 // ---------------------------------------------------------------------------
 // Launchers
 
-template <int D, int MODE>
-static hipError_t launch_mode(int block, bool blind, const StripArgs &a, int grid, size_t lds,
-                              hipStream_t st) {
-    if (block == 256 && !blind)
-        hipLaunchKernelGGL((strip_kernel<D, MODE, 256, false>), dim3(grid), dim3(256), lds, st, a);
-    else if (block == 256)
-        hipLaunchKernelGGL((strip_kernel<D, MODE, 256, true>), dim3(grid), dim3(256), lds, st, a);
-    else if (block == 1024 && !blind)
-        hipLaunchKernelGGL((strip_kernel<D, MODE, 1024, false>), dim3(grid), dim3(1024), lds, st, a);
-    else if (block == 1024)
-        hipLaunchKernelGGL((strip_kernel<D, MODE, 1024, true>), dim3(grid), dim3(1024), lds, st, a);
-    else
-        return hipErrorInvalidValue;
+template <int D, int LAY, bool REGION>
+static hipError_t launch_variant(int mode, int block, const StripArgs &a, int grid, size_t lds,
+                                 hipStream_t st) {
+    switch (mode) {
+        case MODE_MASK:
+            if (block == 512)
+                hipLaunchKernelGGL((strip_kernel<D, MODE_MASK, 512, LAY, REGION>), dim3(grid), dim3(512), lds, st, a);
+            else
+                hipLaunchKernelGGL((strip_kernel<D, MODE_MASK, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+            break;
+        case MODE_OCC:
+            if (block == 1024)
+                hipLaunchKernelGGL((strip_kernel<D, MODE_OCC, 1024, LAY, REGION>), dim3(grid), dim3(1024), lds, st, a);
+            else
+                hipLaunchKernelGGL((strip_kernel<D, MODE_OCC, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+            break;
+        case MODE_MASK | MODE_OCC:
+            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK | MODE_OCC, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+            break;
+        case MODE_OCC | MODE_COUNTS:
+            hipLaunchKernelGGL((strip_kernel<D, MODE_OCC | MODE_COUNTS, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+            break;
+        default:
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template <int D>
-static hipError_t launch_strip_d(int mode, int block, bool blind, const StripArgs &a, int grid,
-                                 size_t lds, hipStream_t st) {
-    switch (mode) {
-        case MODE_MASK:
-            if (block != 256) return hipErrorInvalidValue;
-            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK, 256, false>), dim3(grid), dim3(256), lds, st, a);
-            return hipGetLastError();
-        case MODE_OCC: return launch_mode<D, MODE_OCC>(block, blind, a, grid, lds, st);
-        case MODE_MASK | MODE_OCC: return launch_mode<D, MODE_MASK | MODE_OCC>(block, blind, a, grid, lds, st);
-        case MODE_OCC | MODE_COUNTS: return launch_mode<D, MODE_OCC | MODE_COUNTS>(block, blind, a, grid, lds, st);
-        default: return hipErrorInvalidValue;
+static hipError_t launch_strip_d(int mode, int block, int lay, bool region, const StripArgs &a,
+                                 int grid, size_t lds, hipStream_t st) {
+    if (lay == LAY_WIDE) {
+        if (D > 5) return hipErrorInvalidValue;
+        if (region) return launch_variant<D, (D <= 5 ? LAY_WIDE : LAY_COMPACT), true>(mode, block, a, grid, lds, st);
+        return launch_variant<D, (D <= 5 ? LAY_WIDE : LAY_COMPACT), false>(mode, block, a, grid, lds, st);
     }
+    if (region) return launch_variant<D, LAY_COMPACT, true>(mode, block, a, grid, lds, st);
+    return launch_variant<D, LAY_COMPACT, false>(mode, block, a, grid, lds, st);
+}
+
+size_t strip_lds_bytes(int depth, int mode, int reg_cols, int lay) {
+    if (depth < 1 || depth > 8 || (lay == LAY_WIDE && depth > 5)) return 0;
+    const size_t words = (size_t)reg_cols * (size_t)lds_words(depth, lay);
+    return words * 4 * (((mode & MODE_MASK) ? 1 : 0) + ((mode & MODE_OCC) ? 1 : 0));
 }
 
 // Every pointer a mode writes or reads must be set; a launch with a missing
@@ -388,17 +411,18 @@ static bool strip_pointers_ok(int mode, const StripArgs &a) {
     return true;
 }
 
-hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block, bool blind,
-                        size_t lds_bytes, hipStream_t stream) {
+hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block, int pad,
+                        bool region, size_t lds_bytes, hipStream_t stream) {
     if (!strip_pointers_ok(mode, a) || grid < 1) return hipErrorInvalidValue;
     if (a.frame_pitch > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+    if (!region && a.reg_cols != 1) return hipErrorInvalidValue;
     switch (depth) {
-        case 1: return launch_strip_d<1>(mode, block, blind, a, grid, lds_bytes, stream);
-        case 2: return launch_strip_d<2>(mode, block, blind, a, grid, lds_bytes, stream);
-        case 3: return launch_strip_d<3>(mode, block, blind, a, grid, lds_bytes, stream);
-        case 4: return launch_strip_d<4>(mode, block, blind, a, grid, lds_bytes, stream);
-        case 5: return launch_strip_d<5>(mode, block, blind, a, grid, lds_bytes, stream);
-        case 6: return launch_strip_d<6>(mode, block, blind, a, grid, lds_bytes, stream);
+        case 1: return launch_strip_d<1>(mode, block, pad, region, a, grid, lds_bytes, stream);
+        case 2: return launch_strip_d<2>(mode, block, pad, region, a, grid, lds_bytes, stream);
+        case 3: return launch_strip_d<3>(mode, block, pad, region, a, grid, lds_bytes, stream);
+        case 4: return launch_strip_d<4>(mode, block, pad, region, a, grid, lds_bytes, stream);
+        case 5: return launch_strip_d<5>(mode, block, pad, region, a, grid, lds_bytes, stream);
+        case 6: return launch_strip_d<6>(mode, block, pad, region, a, grid, lds_bytes, stream);
         default: return hipErrorInvalidValue;
     }
 }

@@ -33,26 +33,54 @@ int main() {
         uint32_t d = (uint32_t)(s >> 33) % 100000 + 1, n = (uint32_t)s;
         CHECK(fdiv(n, make_fastdiv(d)) == n / d);
     }
-    // key <-> concat permutation is a bijection and inverse pair; the key of
-    // (R', G', B') is the base-8 path of Algorithm 1
-    for (int d = 1; d <= 8; ++d) {
-        const uint32_t n = 1u << (3 * d);
-        for (uint32_t k = 0; k < n; ++k) {
-            uint32_t j = concat_from_key(k, d);
-            CHECK(j < n);
-            CHECK(key_from_concat(j, d) == k);
-            uint32_t R = j >> (2 * d), G = (j >> d) & ((1u << d) - 1), B = j & ((1u << d) - 1);
-            uint32_t path = 0;
-            for (int i = 0; i < d; ++i) {
-                int b = d - 1 - i;
-                path = path * 8 + (((R >> b) & 1) << 2) + (((G >> b) & 1) << 1) + ((B >> b) & 1);
+    // key <-> LDS index in both LDS orders: inverse pair, injective, inside
+    // the table, and the key of (R', G', B') is the base-8 path of Algorithm 1
+    for (int lay = 0; lay < 2; ++lay) {
+        for (int d = 1; d <= (lay == LAY_WIDE ? 5 : 8); ++d) {
+            const uint32_t n = 1u << (3 * d);
+            const uint32_t lsize = (uint32_t)lds_words(d, lay) * 32u;
+            unsigned char *seen = (unsigned char *)calloc(lsize, 1);
+            for (uint32_t k = 0; k < n; ++k) {
+                uint32_t l = lds_from_key(k, d, lay);
+                CHECK(l < lsize);
+                if (l >= lsize) continue;
+                CHECK(!seen[l]);
+                seen[l] = 1;
+                CHECK(key_from_lds(l, d, lay) == k);
+                uint32_t R, G, B;
+                if (lay == LAY_WIDE) { R = (l >> 5) & ((1u << d) - 1); G = l >> 13; B = l & 31; }
+                else { R = l >> (2 * d); G = (l >> d) & ((1u << d) - 1); B = l & ((1u << d) - 1); }
+                uint32_t path = 0;
+                for (int i = 0; i < d; ++i) {
+                    int b = d - 1 - i;
+                    path = path * 8 + (((R >> b) & 1) << 2) + (((G >> b) & 1) << 1) + ((B >> b) & 1);
+                }
+                CHECK(path == k);
             }
-            CHECK(path == k);
+            free(seen);
+            // splitting a key into high and low bits splits the map too
+            for (uint32_t k = 0; k < n; k += 37)
+                CHECK(lds_from_key(k, d, lay) == (lds_from_key(k & ~31u, d, lay) | lds_from_key(k & 31u, d, lay)));
         }
-        // splitting a key into high and low bits splits the permutation too
-        for (uint32_t k = 0; k < n; k += 37)
-            CHECK(concat_from_key(k, d) == (concat_from_key(k & ~31u, d) | concat_from_key(k & 31u, d)));
     }
+    // wide order: the byte address the kernel forms from a pixel's R,G bytes
+    // is 4 * (L >> 5), and B' is L & 31
+    for (int d = 1; d <= 5; ++d)
+        for (uint32_t R = 0; R < 256; R += 3)
+            for (uint32_t G = 0; G < 256; G += 5)
+                for (uint32_t B = 0; B < 256; B += 7) {
+                    const uint32_t s = 8 - d;
+                    uint32_t k = 0;
+                    for (int i = 0; i < d; ++i) {
+                        int b = 7 - i;
+                        k = k * 8 + (((R >> b) & 1) << 2) + (((G >> b) & 1) << 1) + ((B >> b) & 1);
+                    }
+                    const uint32_t l = lds_from_key(k, d, LAY_WIDE);
+                    const uint32_t rg = (R | (G << 8)) >> (6 - d);          // R byte below G byte
+                    const uint32_t M = (((1u << d) - 1u) << 2) | (((1u << d) - 1u) << 10);
+                    CHECK((rg & M) == 4 * (l >> 5));
+                    CHECK((B >> s) == (l & 31));
+                }
     printf("%s (%d failures)\n", fails ? "FAILED" : "ok", fails);
     return fails ? 1 : 0;
 }
