@@ -145,6 +145,9 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
  *   OBG_TUNE_LAYOUT             LDS order of d <= 5 trees: 1 = wide table
  *                               indexed by the pixel's R,G bytes (default),
  *                               2 = compact
+ *   OBG_TUNE_INTERLEAVE         1 = work items dealt round-robin to the
+ *                               workgroups, 2 = contiguous runs (default:
+ *                               round-robin for classify without regions)
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1
@@ -153,7 +156,8 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
 #define OBG_TUNE_CLASSIFY_SPAN       4
 #define OBG_TUNE_CLASSIFY_BLOCK      5
 #define OBG_TUNE_LAYOUT              6
-#define OBG_TUNE_COUNT               7
+#define OBG_TUNE_INTERLEAVE          7
+#define OBG_TUNE_COUNT               8
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 

@@ -198,6 +198,13 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     const int64_t span = (groups_strip + spans - 1) / spans;
     const int64_t n_items = n_sf * spans;
     if (n_items > 0x7FFFFFFF) return fail(OBG_EINVAL, "too many work items (n_frames too large for one call)");
+    // one tree per strip: the LDS tables never change between items, so
+    // items are dealt round-robin and the workgroups stream through
+    // neighbouring memory; with several regions per strip a workgroup keeps
+    // a contiguous run of items of the same strip
+    a.interleave = (g.reg_cols == 1 && a.n_strips == 1 && !(mode & MODE_OCC))
+                       ? (tune(OBG_TUNE_INTERLEAVE, 1) == 1)
+                       : (tune(OBG_TUNE_INTERLEAVE, 2) == 1);
     a.span = (int32_t)span;
     a.spans = (int32_t)spans;
     a.n_items = (int32_t)n_items;

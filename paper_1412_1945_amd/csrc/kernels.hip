@@ -191,10 +191,20 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((MODE == 
     uint32_t *leaf_lds = REGION ? dyn_lds : st_leaf;
     uint32_t *occ_lds = REGION ? dyn_lds + (MASK ? tiles * LW : 0) : st_occ;
 
-    const int i0 = (int)((int64_t)a.n_items * blockIdx.x / gridDim.x);
-    const int i1 = (int)((int64_t)a.n_items * (blockIdx.x + 1) / gridDim.x);
+    // work items: a contiguous range per workgroup, or interleaved so that
+    // the items in flight at any moment are neighbours in memory
+    int i0, i1, istep;
+    if (a.interleave) {
+        i0 = blockIdx.x;
+        i1 = a.n_items;
+        istep = gridDim.x;
+    } else {
+        i0 = (int)((int64_t)a.n_items * blockIdx.x / gridDim.x);
+        i1 = (int)((int64_t)a.n_items * (blockIdx.x + 1) / gridDim.x);
+        istep = 1;
+    }
     int cur_s = -1, cur_f = -1;
-    for (int it = i0; it < i1; ++it) {
+    for (int it = i0; it < i1; it += istep) {
         const int sf = it / a.spans;
         const int t = it - sf * a.spans;
         const int s = sf / a.n_frames;
