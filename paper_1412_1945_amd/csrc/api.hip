@@ -195,7 +195,8 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         const int64_t span_groups = tune(OBG_TUNE_CLASSIFY_SPAN, 4096);
         spans = (groups_strip + span_groups - 1) / span_groups;
     }
-    const int64_t span = (groups_strip + spans - 1) / spans;
+    // spans are whole multiples of 4 groups (one 64-pixel mask word)
+    const int64_t span = (((groups_strip + spans - 1) / spans) + 3) & ~(int64_t)3;
     const int64_t n_items = n_sf * spans;
     if (n_items > 0x7FFFFFFF) return fail(OBG_EINVAL, "too many work items (n_frames too large for one call)");
     // one tree per strip: the LDS tables never change between items, so

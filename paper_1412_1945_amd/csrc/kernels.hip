@@ -85,6 +85,7 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
 // that only write zero mask bits need no separate load path.
 
 typedef __attribute__((ext_vector_type(4))) unsigned int v4u;
+typedef __attribute__((ext_vector_type(2))) unsigned int v2u;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
@@ -167,9 +168,20 @@ __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffe
     else
         present = group_pixels<D, MODE, PAD, true>(u, nv, leaf_tile, occ_tile, cnt);
     if (MASK) {
+        // Four consecutive lanes hold the four 16-pixel groups of one 64-pixel
+        // mask word (work spans and rows are multiples of 4 groups): gather
+        // them with quad permutes and let the first lane of the quad write the
+        // whole aligned 64-bit word.
         const uint32_t valid = 0xFFFFu >> (16 - nv);
-        const uint32_t off = yr * (uint32_t)a.mask_row_words * 8u + 2u * gx;
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(~present & valid), ms, off, 0, 0);
+        const uint32_t m16 = ~present & valid;
+        const uint32_t n1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x39, 0xF, 0xF, false);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x4E, 0xF, 0xF, false);
+        const uint32_t n3 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x93, 0xF, 0xF, false);
+        if ((threadIdx.x & 3) == 0) {
+            const uint32_t off = yr * (uint32_t)a.mask_row_words * 8u + 2u * gx;
+            const uint32_t lo = m16 | (n1 << 16), hi = n2 | (n3 << 16);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, make_uint2(lo, hi)), ms, off, 0, 0);
+        }
     }
 }
 
