@@ -148,6 +148,9 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
  *   OBG_TUNE_INTERLEAVE         1 = work items dealt round-robin to the
  *                               workgroups, 2 = contiguous runs (default:
  *                               round-robin for classify without regions)
+ *   OBG_TUNE_MASK_STAGE         1 = gather a work item's mask in LDS and write
+ *                               it in one run (items of <= 1024 groups),
+ *                               2 = write each 64-pixel word directly (default)
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1
@@ -157,7 +160,8 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
 #define OBG_TUNE_CLASSIFY_BLOCK      5
 #define OBG_TUNE_LAYOUT              6
 #define OBG_TUNE_INTERLEAVE          7
-#define OBG_TUNE_COUNT               8
+#define OBG_TUNE_MASK_STAGE          8
+#define OBG_TUNE_COUNT               9
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 

@@ -206,6 +206,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.interleave = (g.reg_cols == 1 && a.n_strips == 1 && !(mode & MODE_OCC))
                        ? (tune(OBG_TUNE_INTERLEAVE, 1) == 1)
                        : (tune(OBG_TUNE_INTERLEAVE, 2) == 1);
+    a.stage_mask = ((mode & MODE_MASK) && span <= 1024) ? (tune(OBG_TUNE_MASK_STAGE, 2) == 1) : 0;
     a.span = (int32_t)span;
     a.spans = (int32_t)spans;
     a.n_items = (int32_t)n_items;

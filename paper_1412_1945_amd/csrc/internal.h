@@ -26,6 +26,7 @@ struct StripArgs {
     int32_t spans;            // work items per (strip, frame)
     int32_t n_items;          // n_strips * n_frames * spans
     int32_t interleave;       // 1: item i goes to workgroup i % grid; 0: contiguous ranges
+    int32_t stage_mask;       // 1: masks gathered in LDS per item (span <= 1024 groups)
     const uint32_t *leaf;     // [n_regions][words], key order
     uint64_t *mask;           // [n_frames][height][mask_row_words]
     int32_t mask_row_words;

@@ -87,6 +87,8 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
 typedef __attribute__((ext_vector_type(4))) unsigned int v4u;
 typedef __attribute__((ext_vector_type(2))) unsigned int v2u;
 
+constexpr int kStageGroups = 1024;
+
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
@@ -147,7 +149,7 @@ template <int D, int MODE, int PAD, bool REGION>
 __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffer_rsrc_t ms,
                                               const uint32_t (&u)[12], uint32_t yr, uint32_t gx,
                                               const uint32_t *leaf_lds, uint32_t *occ_lds,
-                                              uint32_t *__restrict__ cbase) {
+                                              uint32_t *__restrict__ cbase, uint16_t *stage, int gl) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
     constexpr int LW = lds_words(D, PAD);
@@ -174,6 +176,11 @@ __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffe
         // whole aligned 64-bit word.
         const uint32_t valid = 0xFFFFu >> (16 - nv);
         const uint32_t m16 = ~present & valid;
+        if (stage) {
+            // the item's mask bytes are written out together at its end
+            stage[gl] = (uint16_t)m16;
+            return;
+        }
         const uint32_t n1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x39, 0xF, 0xF, false);
         const uint32_t n2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x4E, 0xF, 0xF, false);
         const uint32_t n3 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x93, 0xF, 0xF, false);
@@ -198,6 +205,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((MODE == 
     extern __shared__ uint32_t dyn_lds[];
     __shared__ uint32_t st_leaf[(!REGION && MASK) ? LW : 1];
     __shared__ uint32_t st_occ[(!REGION && OCC) ? LW : 1];
+    // mask staging: one work item's 16-bit group masks (spans <= kStageGroups)
+    __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
+    uint16_t *stage = (MASK && a.stage_mask) ? st_mask : nullptr;
     const int tid = threadIdx.x;
     const int tiles = REGION ? a.reg_cols : 1;
     uint32_t *leaf_lds = REGION ? dyn_lds : st_leaf;
@@ -262,10 +272,22 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((MODE == 
         for (; g < ge; g += 2 * BLOCK) {
             const int g1 = g + BLOCK;
             if (g1 < ge) fetch_group(rs, a, g1, ub, yb, xb);
-            consume_group<D, MODE, PAD, REGION>(a, ms, ua, ya, xa, leaf_lds, occ_lds, cbase);
+            consume_group<D, MODE, PAD, REGION>(a, ms, ua, ya, xa, leaf_lds, occ_lds, cbase, stage, g - gb);
             const int g2 = g + 2 * BLOCK;
             if (g2 < ge) fetch_group(rs, a, g2, ua, ya, xa);
-            if (g1 < ge) consume_group<D, MODE, PAD, REGION>(a, ms, ub, yb, xb, leaf_lds, occ_lds, cbase);
+            if (g1 < ge)
+                consume_group<D, MODE, PAD, REGION>(a, ms, ub, yb, xb, leaf_lds, occ_lds, cbase, stage, g1 - gb);
+        }
+        if (MASK && a.stage_mask) {
+            // group g's 16 mask bits are bytes 2g, 2g+1 of the strip's mask,
+            // so the item's mask is one contiguous run: write it in 8-byte words
+            __syncthreads();
+            const int n8 = (ge - gb) >> 2;
+            const uint2 *src = reinterpret_cast<const uint2 *>(st_mask);
+            for (int i = tid; i < n8; i += BLOCK)
+                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, src[i]), ms,
+                                                      2u * (uint32_t)gb + 8u * (uint32_t)i, 0, 0);
+            __syncthreads();
         }
     }
     if (OCC && cur_f >= 0) {

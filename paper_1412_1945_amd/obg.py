@@ -182,7 +182,7 @@ def obg_classify(g: FrameGeom, rgb: torch.Tensor, n_frames: int, leafset: torch.
 
 
 TUNE_KEYS = {"train_block": 0, "occ_blind": 1, "occ_wg_per_cu": 2,
-             "classify_wg_per_cu": 3, "classify_span": 4, "classify_block": 5, "layout": 6, "interleave": 7}
+             "classify_wg_per_cu": 3, "classify_span": 4, "classify_block": 5, "layout": 6, "interleave": 7, "mask_stage": 8}
 
 
 def obg_tune_set(key, value: int):
