@@ -138,10 +138,10 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
  *   OBG_TUNE_OCC_WG_PER_CU      workgroups per CU of passes that build
  *                               occupancy (default 2 at 1024 threads, else 4)
  *   OBG_TUNE_CLASSIFY_WG_PER_CU workgroups per CU of classify-only passes
- *                               (default: as many as LDS and waves allow)
- *   OBG_TUNE_CLASSIFY_SPAN      16-pixel groups per work item (default 4096)
+ *                               (default 2, fewer if LDS does not allow)
+ *   OBG_TUNE_CLASSIFY_SPAN      16-pixel groups per work item (default 512)
  *   OBG_TUNE_CLASSIFY_BLOCK     threads per workgroup of classify-only
- *                               passes: 256 (default) or 512
+ *                               passes: 256 or 512 (default)
  *   OBG_TUNE_LAYOUT             LDS order of d <= 5 trees: 1 = wide table
  *                               indexed by the pixel's R,G bytes (default),
  *                               2 = compact
@@ -149,8 +149,8 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
  *                               workgroups, 2 = contiguous runs (default:
  *                               round-robin for classify without regions)
  *   OBG_TUNE_MASK_STAGE         1 = gather a work item's mask in LDS and write
- *                               it in one run (items of <= 1024 groups),
- *                               2 = write each 64-pixel word directly (default)
+ *                               it in one run (items of <= 1024 groups;
+ *                               default), 2 = write each 64-pixel word directly
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1

@@ -164,8 +164,8 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     // groups keep the CU at its 32 waves with 4 of them
     const size_t lds_need = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
     const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024)
-                               : (mode == MODE_MASK ? tune(OBG_TUNE_CLASSIFY_BLOCK, lds_need > 20 * 1024 ? 512 : 256)
-                                                    : 256);
+                               : (mode == MODE_MASK ? tune(OBG_TUNE_CLASSIFY_BLOCK, 512) : 256);
+    (void)lds_need;
     if (occ_only && block != 256 && block != 1024) return fail(OBG_EINVAL, "train block size must be 256 or 1024");
     if (!occ_only && block != 256 && block != 512) return fail(OBG_EINVAL, "classify block size must be 256 or 512");
     const size_t lds = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
@@ -189,10 +189,12 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         if (spans > cap) spans = cap;
         if (spans < 1) spans = 1;
     } else {
-        int want = tune(OBG_TUNE_CLASSIFY_WG_PER_CU, per_cu);
+        // measured on the 1080p stream: two 512-thread groups per CU streaming
+        // 512-group items round-robin give the highest read+write rate
+        int want = tune(OBG_TUNE_CLASSIFY_WG_PER_CU, 2);
         if (want > per_cu) want = per_cu;
         target = (int64_t)cus * want;
-        const int64_t span_groups = tune(OBG_TUNE_CLASSIFY_SPAN, 4096);
+        const int64_t span_groups = tune(OBG_TUNE_CLASSIFY_SPAN, 512);
         spans = (groups_strip + span_groups - 1) / span_groups;
     }
     // spans are whole multiples of 4 groups (one 64-pixel mask word)
@@ -206,7 +208,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.interleave = (g.reg_cols == 1 && a.n_strips == 1 && !(mode & MODE_OCC))
                        ? (tune(OBG_TUNE_INTERLEAVE, 1) == 1)
                        : (tune(OBG_TUNE_INTERLEAVE, 2) == 1);
-    a.stage_mask = ((mode & MODE_MASK) && span <= 1024) ? (tune(OBG_TUNE_MASK_STAGE, 2) == 1) : 0;
+    a.stage_mask = ((mode & MODE_MASK) && span <= 1024) ? (tune(OBG_TUNE_MASK_STAGE, 1) == 1) : 0;
     a.span = (int32_t)span;
     a.spans = (int32_t)spans;
     a.n_items = (int32_t)n_items;

@@ -206,3 +206,33 @@ def test_zero_frames_is_noop(env):
     obg.obg_train_frame(g, dummy, 0, occ)
     torch.cuda.synchronize()
     assert int(occ[0, 0, 0]) == 7
+
+
+KNOBS = [
+    {},
+    {"layout": 2},
+    {"mask_stage": 2},
+    {"interleave": 2},
+    {"classify_block": 256, "classify_span": 4096, "classify_wg_per_cu": 4},
+    {"classify_span": 100, "mask_stage": 1},
+    {"train_block": 256, "occ_wg_per_cu": 8},
+    {"occ_wg_per_cu": 1},
+]
+
+
+@pytest.mark.parametrize("knobs", KNOBS, ids=[",".join(f"{k}={v}" for k, v in kn.items()) or "default" for kn in KNOBS])
+def test_launch_knobs_do_not_change_results(env, knobs):
+    """Every launch shape gives the same bytes as the oracle (no LDS or atomic races)."""
+    obg, O = env
+    rng = np.random.default_rng(4242)
+    cases = [(160, 24, 4, 0, 0), (333, 17, 5, 0, 0), (96, 40, 3, 32, 16), (200, 30, 6, 0, 0)]
+    try:
+        for k, v in knobs.items():
+            obg.obg_tune_set(k, v)
+        for W, H, d, rw, rh in cases:
+            rp = ((3 * W + 15) // 16) * 16
+            frames = brute.tiny_frames(rng, 6, W, H, n_colours=11, row_pitch=rp)
+            check_against_oracle(env, W, H, d, frames, 4, 1, 2, rw=rw, rh=rh, label=f"knobs{knobs}")
+    finally:
+        for k in obg.TUNE_KEYS:
+            obg.obg_tune_set(k, 0)
