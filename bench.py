@@ -38,7 +38,41 @@ def parse():
                    help="test frames in the oracle's timed sample")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "classify_traffic.json"),
                    help="HBM traffic of the classify kernel measured with rocprofv3 counters")
+    p.add_argument("--probe", action="store_true",
+                   help="only run the streaming probes (read, read+write, 1 GiB copy) and print them")
     return p.parse_args()
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("kernels.hip", "device.h", "internal.h", "api.hip"):
+        with open(os.path.join(ROOT, "paper_1412_1945_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def run_probes(obg, torch, src, nbytes, reps=5):
+    """Achievable streaming rates for the classify access pattern (TB/s)."""
+    dst = torch.empty(max(nbytes // 24, 1 << 30) + 4096, dtype=torch.uint8, device=src.device)
+    sink = torch.empty(512 * 512, dtype=torch.int32, device=src.device)
+    out = {}
+    for name, kind, n in [("read", obg.PROBE_READ, nbytes), ("read_write", obg.PROBE_READ_WRITE, nbytes),
+                          ("copy_1gib", obg.PROBE_COPY, 1 << 30)]:
+        times = []
+        for r in range(reps + 1):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            obg.obg_probe(kind, src, dst, n, sink, 512)
+            b.record()
+            torch.cuda.synchronize()
+            if r:
+                times.append(a.elapsed_time(b))
+        ms = min(times)
+        moved = n * (2 if kind == obg.PROBE_COPY else 1) + (n // 24 if kind == obg.PROBE_READ_WRITE else 0)
+        out[name] = {"ms": round(ms, 4), "tb_s": round(moved / (ms * 1e-3) / 1e12, 3)}
+    return out
 
 
 def workload(name, n_test):
@@ -89,6 +123,12 @@ def main():
     T, N = spec.n_train, spec.n_test
     print(f"# generating {T}+{N} frames {spec.width}x{spec.height} on the GPU", file=sys.stderr, flush=True)
     frames = torch.empty((T + N, spec.height, spec.row_pitch), dtype=torch.uint8, device=dev)
+    if a.probe:
+        flat = frames.view(-1)
+        nbytes = (N * spec.height * spec.row_pitch // (48 * 512)) * (48 * 512)
+        flat.fill_(7)
+        print(json.dumps({"probe": run_probes(obg, torch, flat, nbytes), "bytes": nbytes}), flush=True)
+        return
     chunk = 50
     for i in range(0, T + N, chunk):
         ids = list(range(i, min(T + N, i + chunk)))
@@ -142,10 +182,12 @@ def main():
     if os.path.exists(a.traffic_json):
         try:
             tj = json.load(open(a.traffic_json))
-            if tj.get("workload") == wl.name and tj.get("n_test") == N:
+            if (tj.get("workload") == wl.name and tj.get("n_test") == N
+                    and tj.get("source_hash") == kernel_source_hash()):
                 traffic = tj.get("bytes_per_launch")
         except (OSError, ValueError):
             traffic = None
+    probes = run_probes(obg, torch, test.reshape(-1), (N * spec.height * spec.row_pitch // (48 * 512)) * (48 * 512))
 
     out = {
         "metric": "train+classify Gpixel/s",
@@ -166,10 +208,12 @@ def main():
         "classify": {"ms_avg": round(cls_avg, 4), "ms_p50": round(cls_ms[len(cls_ms) // 2], 4),
                      "gpixel_s": round(N * spec.pixels / (cls_avg * 1e-3) / 1e9, 3)},
         "train_merge_ms": round(ms_step - cls_avg, 4),
+        "probe": probes,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "strip_kernel (classify)",
-                     "bytes_per_launch": cls_bytes},
+                     "bytes_per_launch": cls_bytes,
+                     "frac_of_read_write_probe": round(achieved / 1000 / probes["read_write"]["tb_s"], 4)},
     }
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)

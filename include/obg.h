@@ -165,6 +165,24 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 
+/*
+ * Measurement probes (not part of the method): streaming kernels that show
+ * what the memory system delivers for the pixel kernels' access pattern.
+ *   OBG_PROBE_READ       read `bytes` of src in 48-byte steps per lane
+ *                        (whole 24 KiB items only); sink gets grid*512 words
+ *   OBG_PROBE_READ_WRITE the same reads plus 1/24 as many bytes written to
+ *                        dst in one run per item (the classify output ratio)
+ *   OBG_PROBE_COPY       copy `bytes` (multiple of 16) from src to dst
+ * Pointers are device pointers, 16-byte aligned; dst must hold bytes/24
+ * (READ_WRITE) or bytes (COPY); sink must hold grid*512 uint32 (READ*).
+ * grid: workgroups of the READ* kernels, 1..65536.
+ */
+#define OBG_PROBE_READ        1
+#define OBG_PROBE_READ_WRITE  2
+#define OBG_PROBE_COPY        3
+int obg_probe(int kind, const void *src, void *dst, int64_t bytes, uint32_t *sink, int32_t grid,
+              hipStream_t stream);
+
 /* Message of the calling thread's last failed call ("" if none). */
 const char *obg_last_error(void);
 

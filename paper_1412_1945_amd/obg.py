@@ -56,6 +56,7 @@ def load() -> ctypes.CDLL:
             "obg_classify": (ctypes.c_int, [G, P, I32, P, P, P, P]),
             "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
+            "obg_probe": (ctypes.c_int, [ctypes.c_int, P, P, I64, P, I32, P]),
             "obg_last_error": (ctypes.c_char_p, []),
             "obg_version": (ctypes.c_char_p, []),
         }
@@ -69,8 +70,8 @@ def load() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
-            "obg_merge", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_last_error",
-            "obg_version"]
+            "obg_merge", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_probe",
+            "obg_last_error", "obg_version"]
 
 
 @dataclass
@@ -193,6 +194,24 @@ def obg_tune_set(key, value: int):
 def obg_tune_get(key) -> int:
     k = TUNE_KEYS[key] if isinstance(key, str) else key
     return load().obg_tune_get(k)
+
+
+PROBE_READ, PROBE_READ_WRITE, PROBE_COPY = 1, 2, 3
+
+
+def obg_probe(kind: int, src: torch.Tensor, dst: Optional[torch.Tensor], nbytes: int,
+              sink: Optional[torch.Tensor], grid: int = 512, stream=None):
+    _need(src, torch.uint8, nbytes, "src")
+    if dst is not None:
+        _need(dst, torch.uint8, 0, "dst")
+        need = nbytes if kind == PROBE_COPY else nbytes // 24
+        if dst.numel() < need:
+            raise ValueError(f"dst holds {dst.numel()} bytes, needs {need}")
+    if sink is not None:
+        _need(sink, torch.int32, grid * 512, "sink")
+    rc = load().obg_probe(kind, _ptr(src), _ptr(dst), nbytes, _ptr(sink), grid, _stream(stream))
+    if rc != OBG_OK:
+        raise ObgError(rc, "probe arguments rejected")
 
 
 def obg_version() -> str:
