@@ -34,7 +34,7 @@ def parse():
                    choices=["plain1080", "region4k", "small"])
     p.add_argument("--n-test", type=int, default=None, help="override the number of test frames")
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-test", type=int, default=350,
+    p.add_argument("--cpu-sample-test", type=int, default=900,
                    help="test frames in the oracle's timed sample")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "classify_traffic.json"),
                    help="HBM traffic of the classify kernel measured with rocprofv3 counters")
