@@ -25,7 +25,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 def build(mutant: int = 0, out: Optional[str] = None) -> str:
     """Compile the oracle with gcc (a planted-mistake variant when mutant > 0)."""
     out = out or (LIB if mutant == 0 else os.path.join(HERE, f"liboracle_m{mutant}.so"))
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-pthread",
            f"-DORC_MUTANT={mutant}", "-o", out + ".tmp", SRC]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
@@ -54,6 +54,7 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "orc_classify": (_I, [_P, _P, _I64, _P]),
         "orc_check_pixel": (_I, [_P, _I, _I, ctypes.c_uint8, ctypes.c_uint8, ctypes.c_uint8]),
         "orc_model_free": (None, [_P]),
+        "orc_release_pool": (None, []),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

@@ -47,6 +47,7 @@
  *   mask: per row ceil(W / 64) 64-bit words, pixel x at bit (x & 63) of word
  *     (x >> 6), 1 = foreground, bits past the row end 0.
  */
+#include <pthread.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -72,7 +73,42 @@ typedef struct Arena {
     size_t used;       /* nodes used in the last block */
 } Arena;
 
-#define ARENA_BLOCK 4096
+/* One arena holds every tree of a frame (or of a merged model), so that the
+ * nodes of thousands of small region trees come from a few large blocks. */
+#define ARENA_BLOCK 8192
+
+/* Freed blocks are kept for reuse, so that building frame after frame does
+ * not map fresh memory each time (page faults dominate otherwise). */
+static pthread_mutex_t pool_mu = PTHREAD_MUTEX_INITIALIZER;
+static Node **pool;
+static size_t pool_n, pool_cap;
+
+static Node *block_get(void) {
+    Node *blk = NULL;
+    pthread_mutex_lock(&pool_mu);
+    if (pool_n) blk = pool[--pool_n];
+    pthread_mutex_unlock(&pool_mu);
+    if (blk) {
+        memset(blk, 0, ARENA_BLOCK * sizeof(Node));
+        return blk;
+    }
+    blk = (Node *)calloc(ARENA_BLOCK, sizeof(Node));
+    if (!blk) abort();
+    return blk;
+}
+
+static void block_put(Node *blk) {
+    pthread_mutex_lock(&pool_mu);
+    if (pool_n == pool_cap) {
+        size_t nc = pool_cap ? pool_cap * 2 : 256;
+        Node **np = (Node **)realloc(pool, nc * sizeof(Node *));
+        if (!np) abort();
+        pool = np;
+        pool_cap = nc;
+    }
+    pool[pool_n++] = blk;
+    pthread_mutex_unlock(&pool_mu);
+}
 
 static Node *new_node(Arena *a) {
     if (a->nblocks == 0 || a->used == ARENA_BLOCK) {
@@ -83,28 +119,35 @@ static Node *new_node(Arena *a) {
             a->blocks = nb;
             a->cap = nc;
         }
-        Node *blk = (Node *)calloc(ARENA_BLOCK, sizeof(Node));
-        if (!blk) abort();
-        a->blocks[a->nblocks++] = blk;
+        a->blocks[a->nblocks++] = block_get();
         a->used = 0;
     }
     return &a->blocks[a->nblocks - 1][a->used++];
 }
 
 static void arena_free(Arena *a) {
-    for (size_t i = 0; i < a->nblocks; ++i) free(a->blocks[i]);
+    for (size_t i = 0; i < a->nblocks; ++i) block_put(a->blocks[i]);
     free(a->blocks);
     memset(a, 0, sizeof(*a));
+}
+
+/* Return pooled blocks to the system (after a large run). */
+void orc_release_pool(void) {
+    pthread_mutex_lock(&pool_mu);
+    for (size_t i = 0; i < pool_n; ++i) free(pool[i]);
+    pool_n = 0;
+    pthread_mutex_unlock(&pool_mu);
 }
 
 static size_t arena_nodes(const Arena *a) {
     return a->nblocks ? (a->nblocks - 1) * ARENA_BLOCK + a->used : 0;
 }
 
-typedef struct Tree {
-    Node *root;
+/* The trees of one frame (or one merged model): a root per region. */
+typedef struct Trees {
+    Node **roots;
     Arena arena;
-} Tree;
+} Trees;
 
 /* ------------------------------------------------------------------------ */
 /* Algorithm 1: Store Color                                                 */
@@ -120,15 +163,15 @@ static int child_index(uint8_t r, uint8_t g, uint8_t b, int level) {
     return (((r >> bit) & 1) << 2) | (((g >> bit) & 1) << 1) | ((b >> bit) & 1);
 }
 
-static void store_color(Tree *t, uint8_t r, uint8_t g, uint8_t b, int levels) {
-    if (t->root == NULL) t->root = new_node(&t->arena);
-    Node *temp = t->root;
+static void store_color(Node **root, Arena *a, uint8_t r, uint8_t g, uint8_t b, int levels) {
+    if (*root == NULL) *root = new_node(a);
+    Node *temp = *root;
     for (int i = 0; i < levels; ++i) {
         int index = child_index(r, g, b, i);
         if (temp->child[index] != NULL) {
             temp = temp->child[index];
         } else {
-            temp->child[index] = new_node(&t->arena);
+            temp->child[index] = new_node(a);
             temp = temp->child[index];
         }
     }
@@ -294,7 +337,7 @@ static uint64_t leaf_words(int depth) {
 typedef struct Forest {
     Geom g;
     int nframes, cap;
-    Tree **trees;      /* [frame] -> array of n_regions trees (NULL if dropped) */
+    Trees **frames;    /* [frame] -> trees of that frame (NULL if dropped) */
 } Forest;
 
 Forest *orc_forest_new(int width, int height, int depth, int region_w, int region_h) {
@@ -306,15 +349,30 @@ Forest *orc_forest_new(int width, int height, int depth, int region_w, int regio
 
 int orc_forest_regions(const Forest *f) { return geom_regions(&f->g); }
 
-static int forest_append(Forest *f, Tree *t) {
+static Trees *trees_new(int nreg) {
+    Trees *t = (Trees *)calloc(1, sizeof(Trees));
+    if (!t) abort();
+    t->roots = (Node **)calloc((size_t)nreg, sizeof(Node *));
+    if (!t->roots) abort();
+    return t;
+}
+
+static void trees_free(Trees *t) {
+    if (!t) return;
+    arena_free(&t->arena);
+    free(t->roots);
+    free(t);
+}
+
+static int forest_append(Forest *f, Trees *t) {
     if (f->nframes == f->cap) {
         int nc = f->cap ? f->cap * 2 : 16;
-        Tree **nt = (Tree **)realloc(f->trees, (size_t)nc * sizeof(Tree *));
+        Trees **nt = (Trees **)realloc(f->frames, (size_t)nc * sizeof(Trees *));
         if (!nt) abort();
-        f->trees = nt;
+        f->frames = nt;
         f->cap = nc;
     }
-    f->trees[f->nframes] = t;
+    f->frames[f->nframes] = t;
     return f->nframes++;
 }
 
@@ -324,25 +382,31 @@ int orc_forest_add_frame(Forest *f, const uint8_t *rgb, int64_t row_pitch, int s
     const Geom *g = &f->g;
     if (store_levels < g->depth || store_levels > 8) return -1;
     int nreg = geom_regions(g);
-    Tree *full = (Tree *)calloc((size_t)nreg, sizeof(Tree));
-    Tree *pruned = (Tree *)calloc((size_t)nreg, sizeof(Tree));
-    if (!full || !pruned) abort();
-    for (int y = 0; y < g->height; ++y) {
-        const uint8_t *row = rgb + (int64_t)y * row_pitch;
-        for (int x = 0; x < g->width; ++x) {
-            const uint8_t *p = row + 3 * x;
-            store_color(&full[region_of(g, x, y)], p[0], p[1], p[2], store_levels);
+    Trees *full = trees_new(nreg);
+    Trees *pruned = trees_new(nreg);
+    /* one tree per region, built from that region's pixels (Section 3) */
+    for (int ry = 0; ry < g->reg_rows; ++ry) {
+        for (int rx = 0; rx < g->reg_cols; ++rx) {
+            const int y0 = ry * g->region_h, x0 = rx * g->region_w;
+            const int y1 = y0 + g->region_h < g->height ? y0 + g->region_h : g->height;
+            const int x1 = x0 + g->region_w < g->width ? x0 + g->region_w : g->width;
+            for (int y = y0; y < y1; ++y) {
+                const uint8_t *row = rgb + (int64_t)y * row_pitch;
+                for (int x = x0; x < x1; ++x) {
+                    const uint8_t *p = row + 3 * x;
+                    store_color(&full->roots[region_of(g, x, y)], &full->arena, p[0], p[1], p[2], store_levels);
+                }
+            }
         }
     }
     for (int r = 0; r < nreg; ++r) {
 #if ORC_MUTANT == 7   /* one level too many removed, then re-grown by the leaf count */
-        pruned[r].root = prune_copy(full[r].root, g->depth > 1 ? g->depth - 1 : 1, &pruned[r].arena);
+        pruned->roots[r] = prune_copy(full->roots[r], g->depth > 1 ? g->depth - 1 : 1, &pruned->arena);
 #else
-        pruned[r].root = prune_copy(full[r].root, g->depth, &pruned[r].arena);
+        pruned->roots[r] = prune_copy(full->roots[r], g->depth, &pruned->arena);
 #endif
-        arena_free(&full[r].arena);
     }
-    free(full);
+    trees_free(full);
     return forest_append(f, pruned);
 }
 
@@ -352,15 +416,14 @@ int orc_forest_add_occupancy(Forest *f, const uint32_t *occ) {
     const Geom *g = &f->g;
     int nreg = geom_regions(g);
     uint64_t words = leaf_words(g->depth), leaves = 1ull << (3 * g->depth);
-    Tree *t = (Tree *)calloc((size_t)nreg, sizeof(Tree));
-    if (!t) abort();
+    Trees *t = trees_new(nreg);
     for (int r = 0; r < nreg; ++r) {
         const uint32_t *w = occ + (uint64_t)r * words;
         for (uint64_t k = 0; k < leaves; ++k) {
             if ((w[k >> 5] >> (k & 31)) & 1u) {
                 uint8_t R, G, B;
                 key_colour(k, g->depth, &R, &G, &B);
-                store_color(&t[r], R, G, B, g->depth);
+                store_color(&t->roots[r], &t->arena, R, G, B, g->depth);
             }
         }
     }
@@ -368,39 +431,36 @@ int orc_forest_add_occupancy(Forest *f, const uint32_t *occ) {
 }
 
 int orc_forest_frame_export(const Forest *f, int frame, uint32_t *occ, uint32_t *counts) {
-    if (frame < 0 || frame >= f->nframes || f->trees[frame] == NULL) return -1;
+    if (frame < 0 || frame >= f->nframes || f->frames[frame] == NULL) return -1;
     const Geom *g = &f->g;
     int nreg = geom_regions(g);
     uint64_t words = leaf_words(g->depth), leaves = 1ull << (3 * g->depth);
     memset(occ, 0, (size_t)(words * nreg) * sizeof(uint32_t));
     if (counts) memset(counts, 0, (size_t)(leaves * nreg) * sizeof(uint32_t));
     for (int r = 0; r < nreg; ++r) {
-        const Tree *t = &f->trees[frame][r];
-        if (t->root)
-            export_leaves(t->root, 0, g->depth, 0, occ + (uint64_t)r * words,
+        const Node *root = f->frames[frame]->roots[r];
+        if (root)
+            export_leaves(root, 0, g->depth, 0, occ + (uint64_t)r * words,
                           counts ? counts + (uint64_t)r * leaves : NULL);
     }
     return 0;
 }
 
 int64_t orc_forest_frame_nodes(const Forest *f, int frame) {
-    if (frame < 0 || frame >= f->nframes || f->trees[frame] == NULL) return -1;
-    int64_t s = 0;
-    for (int r = 0; r < geom_regions(&f->g); ++r) s += (int64_t)arena_nodes(&f->trees[frame][r].arena);
-    return s;
+    if (frame < 0 || frame >= f->nframes || f->frames[frame] == NULL) return -1;
+    return (int64_t)arena_nodes(&f->frames[frame]->arena);
 }
 
 void orc_forest_drop_frame(Forest *f, int frame) {
-    if (frame < 0 || frame >= f->nframes || f->trees[frame] == NULL) return;
-    for (int r = 0; r < geom_regions(&f->g); ++r) arena_free(&f->trees[frame][r].arena);
-    free(f->trees[frame]);
-    f->trees[frame] = NULL;
+    if (frame < 0 || frame >= f->nframes || f->frames[frame] == NULL) return;
+    trees_free(f->frames[frame]);
+    f->frames[frame] = NULL;
 }
 
 void orc_forest_free(Forest *f) {
     if (!f) return;
     for (int i = 0; i < f->nframes; ++i) orc_forest_drop_frame(f, i);
-    free(f->trees);
+    free(f->frames);
     free(f);
 }
 
@@ -409,26 +469,25 @@ void orc_forest_free(Forest *f) {
 
 typedef struct Model {
     Geom g;
-    Tree *trees;       /* [n_regions] */
+    Trees *trees;      /* one merged root per region */
 } Model;
 
 /* Merge the trees of the listed frames, region by region (Algorithm 2). */
 Model *orc_merge(const Forest *f, const int32_t *frames, int n, uint32_t num, uint32_t den) {
     if (n < 1 || den == 0) return NULL;
     for (int j = 0; j < n; ++j)
-        if (frames[j] < 0 || frames[j] >= f->nframes || f->trees[frames[j]] == NULL) return NULL;
+        if (frames[j] < 0 || frames[j] >= f->nframes || f->frames[frames[j]] == NULL) return NULL;
     Model *m = (Model *)calloc(1, sizeof(Model));
     if (!m) abort();
     m->g = f->g;
     int nreg = geom_regions(&f->g);
-    m->trees = (Tree *)calloc((size_t)nreg, sizeof(Tree));
+    m->trees = trees_new(nreg);
     Node **roots = (Node **)malloc((size_t)n * sizeof(Node *));
-    if (!m->trees || !roots) abort();
+    if (!roots) abort();
     for (int r = 0; r < nreg; ++r) {
-        for (int j = 0; j < n; ++j) roots[j] = f->trees[frames[j]][r].root;
-        Tree *t = &m->trees[r];
-        t->root = new_node(&t->arena);
-        merge_into(t->root, roots, n, num, den, f->g.depth, &t->arena);
+        for (int j = 0; j < n; ++j) roots[j] = f->frames[frames[j]]->roots[r];
+        m->trees->roots[r] = new_node(&m->trees->arena);
+        merge_into(m->trees->roots[r], roots, n, num, den, f->g.depth, &m->trees->arena);
     }
     free(roots);
     return m;
@@ -442,15 +501,14 @@ Model *orc_model_from_leafset(int width, int height, int depth, int region_w, in
     if (geom_init(&m->g, width, height, depth, region_w, region_h) != 0) { free(m); return NULL; }
     int nreg = geom_regions(&m->g);
     uint64_t words = leaf_words(depth), leaves = 1ull << (3 * depth);
-    m->trees = (Tree *)calloc((size_t)nreg, sizeof(Tree));
-    if (!m->trees) abort();
+    m->trees = trees_new(nreg);
     for (int r = 0; r < nreg; ++r) {
         const uint32_t *w = leaf + (uint64_t)r * words;
         for (uint64_t k = 0; k < leaves; ++k)
             if ((w[k >> 5] >> (k & 31)) & 1u) {
                 uint8_t R, G, B;
                 key_colour(k, depth, &R, &G, &B);
-                store_color(&m->trees[r], R, G, B, depth);
+                store_color(&m->trees->roots[r], &m->trees->arena, R, G, B, depth);
             }
     }
     return m;
@@ -462,7 +520,7 @@ int orc_model_leafset(const Model *m, uint32_t *leaf, int64_t *dangling) {
     memset(leaf, 0, (size_t)(words * nreg) * sizeof(uint32_t));
     int64_t dang = 0;
     for (int r = 0; r < nreg; ++r) {
-        const Node *root = m->trees[r].root;
+        const Node *root = m->trees->roots[r];
         if (root) {
             export_leaves(root, 0, m->g.depth, 0, leaf + (uint64_t)r * words, NULL);
             dang += (int64_t)count_dangling(root, 0, m->g.depth);
@@ -482,7 +540,7 @@ int orc_classify(const Model *m, const uint8_t *rgb, int64_t row_pitch, uint64_t
         uint64_t *mrow = mask + (size_t)y * mw;
         for (int x = 0; x < g->width; ++x) {
             const uint8_t *p = row + 3 * x;
-            const Node *root = m->trees[region_of(g, x, y)].root;
+            const Node *root = m->trees->roots[region_of(g, x, y)];
 #if ORC_MUTANT == 8   /* polarity inverted */
             if (check_color(root, p[0], p[1], p[2], g->depth))
 #else
@@ -496,13 +554,12 @@ int orc_classify(const Model *m, const uint8_t *rgb, int64_t row_pitch, uint64_t
 
 /* Check Color of one pixel (used for sampled checks of very large runs). */
 int orc_check_pixel(const Model *m, int x, int y, uint8_t r, uint8_t g, uint8_t b) {
-    const Node *root = m->trees[region_of(&m->g, x, y)].root;
+    const Node *root = m->trees->roots[region_of(&m->g, x, y)];
     return check_color(root, r, g, b, m->g.depth);
 }
 
 void orc_model_free(Model *m) {
     if (!m) return;
-    for (int r = 0; r < geom_regions(&m->g); ++r) arena_free(&m->trees[r].arena);
-    free(m->trees);
+    trees_free(m->trees);
     free(m);
 }

@@ -1,0 +1,88 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py times.
+
+The oracle checks every training occupancy and the merged leaf set in full,
+a few whole test frames, and pixels sampled uniformly over every test frame
+(Check Color of each sampled pixel, one by one).
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(oracle_lib):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_1945_amd import obg
+    obg.load()
+    return obg, oracle_lib
+
+
+def _generate(spec, device="cuda"):
+    from synth.frames import make_frames
+    frames = torch.empty((spec.n_frames, spec.height, spec.row_pitch), dtype=torch.uint8, device=device)
+    for i in range(0, spec.n_frames, 50):
+        ids = list(range(i, min(spec.n_frames, i + 50)))
+        make_frames(spec, ids, device=device, out=frames[ids[0]: ids[-1] + 1])
+    return frames
+
+
+def _run_and_check(env, wl, whole_frames, n_samples, seed):
+    obg, O = env
+    spec = wl.streams[0]
+    d = wl.depth[0]
+    num, den = wl.thr[0]
+    rw, rh = wl.region
+    T, N = spec.n_train, spec.n_test
+    print(f"[case] {wl.name}: generating {T}+{N} frames", flush=True)
+    g = obg.FrameGeom(spec.width, spec.height, d, region_w=rw, region_h=rh)
+    frames = _generate(spec)
+    occ = obg.empty_occ(g, T)
+    leaf = obg.empty_leafset(g)
+    mask = obg.empty_mask(g, N)
+    print(f"[case] {wl.name}: train, merge, classify on the GPU", flush=True)
+    obg.obg_train_frame(g, frames[:T], T, occ)
+    obg.obg_merge(g, occ, T, 0, T, num, den, leaf)
+    obg.obg_classify(g, frames[T:], N, leaf, mask)
+    torch.cuda.synchronize()
+    print(f"[case] {wl.name}: oracle trees of {T} frames", flush=True)
+    host_train = frames[:T].cpu().numpy()
+    forest = O.Forest(spec.width, spec.height, d, rw, rh)
+    idx = forest.add_frames(list(host_train))
+    g_occ = occ.cpu().numpy().view(np.uint32)
+    for i in idx:
+        assert np.array_equal(g_occ[i], forest.export(i)), f"occupancy of training frame {i}"
+    model = forest.merge(idx, num, den)
+    assert np.array_equal(leaf.cpu().numpy().view(np.uint32), model.leafset()), "merged leaf set"
+    g_mask = mask.cpu().numpy().view(np.uint64)
+    for t in whole_frames:
+        want = model.classify(frames[T + t].cpu().numpy())
+        assert np.array_equal(g_mask[t], want), f"mask of test frame {t}"
+    rng = np.random.default_rng(seed)
+    fs = rng.integers(0, N, n_samples)
+    ys = rng.integers(0, spec.height, n_samples)
+    xs = rng.integers(0, spec.width, n_samples)
+    px = frames[T + torch.from_numpy(fs).cuda(), torch.from_numpy(ys).cuda()]
+    cols = torch.from_numpy(xs).cuda() * 3
+    rgb = torch.stack([px.gather(1, (cols + c).view(-1, 1)).view(-1) for c in range(3)], dim=1).cpu().numpy()
+    for k in range(n_samples):
+        f, y, x = int(fs[k]), int(ys[k]), int(xs[k])
+        fg = not model.check_pixel(x, y, int(rgb[k, 0]), int(rgb[k, 1]), int(rgb[k, 2]))
+        bit = (int(g_mask[f, y, x >> 6]) >> (x & 63)) & 1
+        assert bit == int(fg), f"pixel ({x},{y}) of test frame {f}"
+    del frames
+    torch.cuda.empty_cache()
+
+
+def test_plain_1080p_full(env):
+    """1920x1080, depth 5, 50 training + 1000 test frames, threshold 1/2."""
+    from synth.frames import cfg1
+    _run_and_check(env, cfg1(), whole_frames=[0, 1, 333, 999], n_samples=20000, seed=1)
+
+
+def test_region_4k_full(env):
+    """3840x2160 in 32x32 regions, depth 4, 30 training + 500 test frames."""
+    from synth.frames import cfg2
+    _run_and_check(env, cfg2(), whole_frames=[0, 499], n_samples=20000, seed=2)
