@@ -128,6 +128,64 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
                  hipStream_t stream);
 
 /*
+ * Batched form: many independent streams of uneven resolution, depth,
+ * training length and threshold.  obg_batch_run enqueues the whole batch as
+ * three steps, each ONE persistent launch over all streams: the per-frame
+ * trees of every training frame (Algorithm 1 + Section 2 pruning), the merge
+ * of every stream's trees with its own threshold (Algorithm 2), and the
+ * foreground masks of every test frame (Algorithm 3).  The steps are captured
+ * once in a HIP graph at creation and replayed.  Outputs are byte-identical
+ * to the one-stream calls (obg_train_frame / obg_merge / obg_classify).
+ *
+ * Each stream: plain geometry (region_w = region_h = 0), depth 1..6,
+ * 1 <= n_train <= 65535 training frames merged as one window (threshold
+ * thr_num/thr_den as in obg_merge), n_test >= 0 test frames.  Buffers are
+ * device pointers owned by the caller and must stay valid while the batch
+ * exists; the batch keeps them (and copies of the descriptors).
+ *   occ     : out, [n_train][ceil(8^d/32)] uint32 (written by every run)
+ *   leafset : out, [ceil(8^d/32)] uint32
+ *   mask    : out, [n_test][height][ceil(width/64)] uint64
+ * flags: OBG_BATCH_AUTOTUNE times launch shapes on the actual buffers (the
+ * call then runs the batch several times and waits for it; every shape is
+ * checked to give the same bytes), OBG_BATCH_NO_GRAPH launches the kernels
+ * directly on every run instead of a captured graph.  `stream` is used only
+ * for those autotuning runs.  Runs of one batch must not overlap.
+ */
+typedef struct obg_stream_desc {
+    obg_geom geom;
+    const uint8_t *train_rgb;
+    int32_t n_train;
+    uint32_t thr_num, thr_den;
+    const uint8_t *test_rgb;
+    int32_t n_test;
+    uint32_t *occ;
+    uint32_t *leafset;
+    uint64_t *mask;
+} obg_stream_desc;
+
+typedef struct obg_batch obg_batch;
+
+#define OBG_BATCH_AUTOTUNE  1u
+#define OBG_BATCH_NO_GRAPH  2u
+
+typedef struct obg_batch_info {
+    int32_t n_streams;
+    int64_t train_items, classify_items;      /* work items of each step   */
+    int64_t pixels_train, pixels_test;        /* pixels one run touches    */
+    int32_t train_block, train_wg_per_cu, train_items_per_wg;
+    int32_t classify_block, classify_wg_per_cu, classify_span;
+    int32_t graph;                            /* 1: runs replay a graph    */
+    int32_t tune_candidates;                  /* shapes timed (autotune)   */
+    double tune_default_ms, tune_best_ms;     /* one run, default vs chosen */
+} obg_batch_info;
+
+int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t flags,
+                     hipStream_t stream, obg_batch **out);
+int obg_batch_run(obg_batch *batch, hipStream_t stream);
+int obg_batch_info_get(const obg_batch *batch, obg_batch_info *out);
+void obg_batch_destroy(obg_batch *batch);
+
+/*
  * Launch-shape knobs of the pixel kernels, process-wide, for the autotuner
  * (0 restores the built-in default).  They change speed only: every setting
  * gives the same bytes.

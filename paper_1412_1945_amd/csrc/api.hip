@@ -24,6 +24,15 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
+}  // namespace
+
+int obg::set_error(int code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+
+namespace {
+
 int hip_fail(hipError_t e, const char *what) {
     return fail(OBG_EHIP, "%s: %s", what, hipGetErrorString(e));
 }

@@ -60,6 +60,9 @@ struct MergeArgs {
 
 enum StripMode { MODE_MASK = 1, MODE_OCC = 2, MODE_COUNTS = 4 };
 
+// Record the calling thread's last error (read by obg_last_error); returns code.
+int set_error(int code, const char *msg);
+
 // lay: LDS order (LAY_WIDE / LAY_COMPACT, see device.h); region: more than
 // one region per strip
 hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int block, int lay,

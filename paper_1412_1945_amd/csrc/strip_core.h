@@ -1,0 +1,267 @@
+// strip_core.h -- per-group device code shared by the strip kernels (one
+// stream per launch) and the batch kernels (many streams per launch).
+#pragma once
+
+#include "internal.h"
+
+namespace obg {
+
+// ---------------------------------------------------------------------------
+// LDS <-> HBM bitset conversion (key order in HBM, LDS order on chip)
+
+// The bits of one key-order word kw are keys 32*kw + b; their LDS indices are
+// lds_from_key(32*kw) | lds_from_key(b) because the map permutes index bits.
+template <int D, int PAD>
+__device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, uint32_t *lds,
+                                            int n_tiles, int tid, int nt) {
+    constexpr int KW = leaf_words(D);
+    constexpr int LW = lds_words(D, PAD);
+    constexpr int LC = leaf_count(D);
+    constexpr int NB = LC < 32 ? LC : 32;
+    for (int i = tid; i < n_tiles * LW; i += nt) lds[i] = 0;
+    __syncthreads();
+    for (int i = tid; i < n_tiles * KW; i += nt) {
+        const int c = i / KW;
+        const int kw = i - c * KW;
+        uint32_t bits = leaf[i];
+        if (LC < 32) bits &= (1u << (LC & 31)) - 1u;
+        if (bits == 0) continue;
+        const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
+        uint32_t *tile = lds + c * LW;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            if ((bits >> b) & 1u) {
+                const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
+                atomicOr(&tile[l >> 5], 1u << (l & 31));
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <int D, int PAD>
+__device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__restrict__ occ,
+                                             int n_tiles, int tid, int nt) {
+    constexpr int KW = leaf_words(D);
+    constexpr int LW = lds_words(D, PAD);
+    constexpr int LC = leaf_count(D);
+    constexpr int NB = LC < 32 ? LC : 32;
+    for (int i = tid; i < n_tiles * KW; i += nt) {
+        const int c = i / KW;
+        const int kw = i - c * KW;
+        const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
+        const uint32_t *tile = lds + c * LW;
+        uint32_t out = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
+            out |= ((tile[l >> 5] >> (l & 31)) & 1u) << b;
+        }
+        if (out) atomicOr(&occ[i], out);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-group work
+//
+// Frames are read through a buffer resource per (frame, strip): offsets are
+// 32-bit and a read past the end of the frame returns zeros instead of
+// faulting, so the partial group at the end of a row and the padding groups
+// that only write zero mask bits need no separate load path.
+
+typedef __attribute__((ext_vector_type(4))) unsigned int v4u;
+typedef __attribute__((ext_vector_type(2))) unsigned int v2u;
+
+constexpr int kStageGroups = 1024;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// Issue the three 16-byte loads of group g (16 pixels = 48 bytes).
+__device__ __forceinline__ void fetch_group(__amdgpu_buffer_rsrc_t rs, const StripArgs &a, int g,
+                                            uint32_t (&u)[12], uint32_t &yr, uint32_t &gx) {
+    yr = fdiv((uint32_t)g, a.div_gpr);
+    gx = (uint32_t)g - yr * (uint32_t)a.gpr;
+    const uint32_t off = yr * (uint32_t)a.row_pitch + 48u * gx;
+    const v4u v0 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+    const v4u v1 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
+    const v4u v2 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 32, 0, 0));
+    u[0] = v0.x; u[1] = v0.y; u[2] = v0.z; u[3] = v0.w;
+    u[4] = v1.x; u[5] = v1.y; u[6] = v1.z; u[7] = v1.w;
+    u[8] = v2.x; u[9] = v2.y; u[10] = v2.z; u[11] = v2.w;
+}
+
+template <int D, int MODE, int PAD, bool GUARD>
+__device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nvalid,
+                                                 const uint32_t *leaf_tile, uint32_t *occ_tile,
+                                                 uint32_t *__restrict__ cnt) {
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    constexpr bool OCC = (MODE & MODE_OCC) != 0;
+    constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
+    uint32_t present = 0;
+    uint32_t run_l = 0xFFFFFFFFu, run_n = 0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        uint32_t addr, bit;
+        lds_pos<D, PAD>(u, p, addr, bit);
+        // mask bits of pixels past the row end are cleared by the caller
+        if (MASK) {
+            const uint32_t w = *reinterpret_cast<const uint32_t *>(
+                reinterpret_cast<const char *>(leaf_tile) + addr);
+            present |= ((w >> (bit & 31)) & 1u) << p;
+        }
+        if ((OCC || CNT) && (!GUARD || p < nvalid)) {
+            if (OCC) atomicOr(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(occ_tile) + addr),
+                              1u << (bit & 31));
+            if (CNT) {
+                const uint32_t l = (addr << 3) | (bit & 31);
+                if (l == run_l) {
+                    ++run_n;
+                } else {
+                    if (run_n) atomicAdd(&cnt[key_from_lds(run_l, D, PAD)], run_n);
+                    run_l = l;
+                    run_n = 1;
+                }
+            }
+        }
+    }
+    if (CNT && run_n) atomicAdd(&cnt[key_from_lds(run_l, D, PAD)], run_n);
+    return present;
+}
+
+template <int D, int MODE, int PAD, bool REGION>
+__device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffer_rsrc_t ms,
+                                              const uint32_t (&u)[12], uint32_t yr, uint32_t gx,
+                                              const uint32_t *leaf_lds, uint32_t *occ_lds,
+                                              uint32_t *__restrict__ cbase, uint16_t *stage, int gl) {
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
+    constexpr int LW = lds_words(D, PAD);
+    constexpr int LC = leaf_count(D);
+    int nv = a.width - (int)gx * 16;
+    nv = nv < 0 ? 0 : (nv > 16 ? 16 : nv);
+    int c = 0;
+    if (REGION) {
+        c = (int)fdiv(gx, a.div_tile);
+        c = c < a.reg_cols ? c : a.reg_cols - 1;     // padding groups: result discarded
+    }
+    const uint32_t *leaf_tile = leaf_lds + c * LW;
+    uint32_t *occ_tile = occ_lds + c * LW;
+    uint32_t *cnt = CNT ? cbase + (int64_t)c * LC : nullptr;
+    uint32_t present;
+    if (nv == 16)
+        present = group_pixels<D, MODE, PAD, false>(u, 16, leaf_tile, occ_tile, cnt);
+    else
+        present = group_pixels<D, MODE, PAD, true>(u, nv, leaf_tile, occ_tile, cnt);
+    if (MASK) {
+        // Four consecutive lanes hold the four 16-pixel groups of one 64-pixel
+        // mask word (work spans and rows are multiples of 4 groups): gather
+        // them with quad permutes and let the first lane of the quad write the
+        // whole aligned 64-bit word.
+        const uint32_t valid = 0xFFFFu >> (16 - nv);
+        const uint32_t m16 = ~present & valid;
+        if (stage) {
+            // the item's mask bytes are written out together at its end
+            stage[gl] = (uint16_t)m16;
+            return;
+        }
+        const uint32_t n1 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x39, 0xF, 0xF, false);
+        const uint32_t n2 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x4E, 0xF, 0xF, false);
+        const uint32_t n3 = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)m16, 0x93, 0xF, 0xF, false);
+        if ((threadIdx.x & 3) == 0) {
+            const uint32_t off = yr * (uint32_t)a.mask_row_words * 8u + 2u * gx;
+            const uint32_t lo = m16 | (n1 << 16), hi = n2 | (n3 << 16);
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, make_uint2(lo, hi)), ms, off, 0, 0);
+        }
+    }
+}
+
+// The groups [gb, ge) of one (frame, strip): two groups in flight per lane
+// (the next group's loads are issued before the current one is worked on);
+// with `stage`, the span's mask is gathered in LDS and written as one run.
+template <int D, int MODE, int PAD, bool REGION, int BLOCK>
+__device__ __forceinline__ void span_loop(const StripArgs &a, __amdgpu_buffer_rsrc_t rs,
+                                          __amdgpu_buffer_rsrc_t ms, int gb, int ge,
+                                          const uint32_t *leaf_lds, uint32_t *occ_lds,
+                                          uint32_t *__restrict__ cbase, uint16_t *stage) {
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    const int tid = threadIdx.x;
+    uint32_t ua[12], ub[12], ya = 0, xa = 0, yb = 0, xb = 0;
+    int g = gb + tid;
+    if (g < ge) fetch_group(rs, a, g, ua, ya, xa);
+    for (; g < ge; g += 2 * BLOCK) {
+        const int g1 = g + BLOCK;
+        if (g1 < ge) fetch_group(rs, a, g1, ub, yb, xb);
+        consume_group<D, MODE, PAD, REGION>(a, ms, ua, ya, xa, leaf_lds, occ_lds, cbase, stage, g - gb);
+        const int g2 = g + 2 * BLOCK;
+        if (g2 < ge) fetch_group(rs, a, g2, ua, ya, xa);
+        if (g1 < ge)
+            consume_group<D, MODE, PAD, REGION>(a, ms, ub, yb, xb, leaf_lds, occ_lds, cbase, stage, g1 - gb);
+    }
+    if (MASK && stage) {
+        // group g's 16 mask bits are bytes 2g, 2g+1 of the strip's mask, so
+        // the span's mask is one contiguous run: write it in 8-byte words
+        __syncthreads();
+        const int n8 = (ge - gb) >> 2;
+        const uint2 *src = reinterpret_cast<const uint2 *>(stage);
+        for (int i = tid; i < n8; i += BLOCK)
+            __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2u, src[i]), ms,
+                                                  2u * (uint32_t)gb + 8u * (uint32_t)i, 0, 0);
+        __syncthreads();
+    }
+}
+
+// One merged word (32 keys) of Algorithm 2 in closed form: bit-sliced
+// counters of the window's bitsets, then a bit-sliced compare with kmin.
+__device__ __forceinline__ uint32_t merge_word(const uint32_t *__restrict__ ring, int ring_len, int first,
+                                               int n_trees, int64_t slot_words, int64_t i, int valid_bits,
+                                               uint32_t kmin, int planes, int empty) {
+    const uint32_t valid = valid_bits >= 32 ? 0xFFFFFFFFu : ((1u << valid_bits) - 1u);
+    if (empty) return 0;
+    uint32_t c[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) c[b] = 0;
+    // eight window slots per round: their loads are independent and in flight together
+    int slot = first;
+    for (int t0 = 0; t0 < n_trees; t0 += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            x[k] = 0;
+            if (t0 + k < n_trees) {
+                int sl = slot + k;
+                if (sl >= ring_len) sl -= ring_len;
+                x[k] = ring[(int64_t)sl * slot_words + i] & valid;
+            }
+        }
+        slot += 8;
+        while (slot >= ring_len) slot -= ring_len;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            uint32_t carry = x[k];
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                if (b < planes) {
+                    const uint32_t tmp = c[b] & carry;
+                    c[b] ^= carry;
+                    carry = tmp;
+                }
+            }
+        }
+    }
+    uint32_t ge = 0, eq = 0xFFFFFFFFu;
+#pragma unroll
+    for (int b = 15; b >= 0; --b) {
+        if ((kmin >> b) & 1u) {
+            eq &= c[b];
+        } else {
+            ge |= eq & c[b];
+            eq &= ~c[b];
+        }
+    }
+    ge |= eq;
+    return ge & valid;
+}
+
+}  // namespace obg

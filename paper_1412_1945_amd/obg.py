@@ -35,6 +35,30 @@ class Geom(ctypes.Structure):
     ]
 
 
+class StreamDesc(ctypes.Structure):
+    _fields_ = [
+        ("geom", Geom),
+        ("train_rgb", ctypes.c_void_p), ("n_train", ctypes.c_int32),
+        ("thr_num", ctypes.c_uint32), ("thr_den", ctypes.c_uint32),
+        ("test_rgb", ctypes.c_void_p), ("n_test", ctypes.c_int32),
+        ("occ", ctypes.c_void_p), ("leafset", ctypes.c_void_p), ("mask", ctypes.c_void_p),
+    ]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_streams", ctypes.c_int32),
+        ("train_items", ctypes.c_int64), ("classify_items", ctypes.c_int64),
+        ("pixels_train", ctypes.c_int64), ("pixels_test", ctypes.c_int64),
+        ("train_block", ctypes.c_int32), ("train_wg_per_cu", ctypes.c_int32),
+        ("train_items_per_wg", ctypes.c_int32),
+        ("classify_block", ctypes.c_int32), ("classify_wg_per_cu", ctypes.c_int32),
+        ("classify_span", ctypes.c_int32),
+        ("graph", ctypes.c_int32), ("tune_candidates", ctypes.c_int32),
+        ("tune_default_ms", ctypes.c_double), ("tune_best_ms", ctypes.c_double),
+    ]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -57,6 +81,11 @@ def load() -> ctypes.CDLL:
             "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
             "obg_probe": (ctypes.c_int, [ctypes.c_int, P, P, I64, P, I32, P]),
+            "obg_batch_create": (ctypes.c_int, [ctypes.POINTER(StreamDesc), I32, U32, P,
+                                                ctypes.POINTER(ctypes.c_void_p)]),
+            "obg_batch_run": (ctypes.c_int, [P, P]),
+            "obg_batch_info_get": (ctypes.c_int, [P, ctypes.POINTER(BatchInfo)]),
+            "obg_batch_destroy": (None, [P]),
             "obg_last_error": (ctypes.c_char_p, []),
             "obg_version": (ctypes.c_char_p, []),
         }
@@ -71,6 +100,7 @@ def load() -> ctypes.CDLL:
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
             "obg_merge", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_probe",
+            "obg_batch_create", "obg_batch_run", "obg_batch_info_get", "obg_batch_destroy",
             "obg_last_error", "obg_version"]
 
 
@@ -212,6 +242,62 @@ def obg_probe(kind: int, src: torch.Tensor, dst: Optional[torch.Tensor], nbytes:
     rc = load().obg_probe(kind, _ptr(src), _ptr(dst), nbytes, _ptr(sink), grid, _stream(stream))
     if rc != OBG_OK:
         raise ObgError(rc, "probe arguments rejected")
+
+
+BATCH_AUTOTUNE, BATCH_NO_GRAPH = 1, 2
+
+
+class Batch:
+    """Owner of an obg_batch handle plus references to its buffers (the library
+    keeps their device pointers, so they must outlive the batch)."""
+
+    def __init__(self, handle, keep):
+        self.h = handle
+        self._keep = keep
+
+    def run(self, stream=None):
+        _check(load().obg_batch_run(self.h, _stream(stream)))
+
+    def info(self) -> dict:
+        bi = BatchInfo()
+        _check(load().obg_batch_info_get(self.h, ctypes.byref(bi)))
+        return {name: getattr(bi, name) for name, _ in BatchInfo._fields_}
+
+    def close(self):
+        if self.h:
+            load().obg_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def obg_batch_create(streams, flags: int = 0, stream=None) -> Batch:
+    """streams: list of dicts with keys geom (FrameGeom), train (uint8 tensor),
+    n_train, thr (num, den), test (uint8 tensor or None), n_test, occ, leafset,
+    mask (tensors as for the one-stream calls)."""
+    arr = (StreamDesc * len(streams))()
+    keep = []
+    for i, sd in enumerate(streams):
+        g = sd["geom"]
+        _frames_ok(g, sd["train"], sd["n_train"])
+        _need(sd["occ"], torch.int32, sd["n_train"] * g.words, "occ")
+        _need(sd["leafset"], torch.int32, g.words, "leafset")
+        if sd["n_test"] > 0:
+            _frames_ok(g, sd["test"], sd["n_test"])
+            _need(sd["mask"], torch.int64, sd["n_test"] * g.height * g.mask_row_words, "mask")
+        num, den = sd["thr"]
+        arr[i] = StreamDesc(g.c(), sd["train"].data_ptr(), sd["n_train"], num, den,
+                            sd["test"].data_ptr() if sd["n_test"] > 0 else None, sd["n_test"],
+                            sd["occ"].data_ptr(), sd["leafset"].data_ptr(),
+                            sd["mask"].data_ptr() if sd["n_test"] > 0 else None)
+        keep.append(sd)
+    h = ctypes.c_void_p()
+    _check(load().obg_batch_create(arr, len(streams), flags, _stream(stream), ctypes.byref(h)))
+    return Batch(h, keep)
 
 
 def obg_version() -> str:

@@ -124,3 +124,21 @@ def test_binding_refuses_cpu_tensors(lib):
     with pytest.raises(ValueError):
         lib.obg_train_frame(g, torch.zeros(16 * 4 * 3, dtype=torch.uint8), 1,
                             torch.zeros(16, dtype=torch.int32))
+
+
+def test_batch_rejects_bad_streams(lib):
+    import ctypes as C
+    L = _raw(lib)
+    g = _geom(lib)
+    good = dict(geom=g, train_rgb=FAKE.value, n_train=4, thr_num=1, thr_den=2, test_rgb=FAKE.value,
+                n_test=2, occ=FAKE.value, leafset=FAKE.value, mask=FAKE.value)
+    out = C.c_void_p()
+    for bad, code in [(dict(n_train=0), -1), (dict(thr_num=0), -1), (dict(occ=None), -1),
+                      (dict(geom=_geom(lib, depth=7)), -1), (dict(geom=_geom(lib, region_w=16, region_h=16)), -1),
+                      (dict(train_rgb=0x100008), -2)]:
+        d = dict(good)
+        d.update(bad)
+        arr = (lib.StreamDesc * 1)(lib.StreamDesc(**d))
+        assert L.obg_batch_create(arr, 1, 0, None, C.byref(out)) == code, (bad, L.obg_last_error())
+        assert not out.value
+    assert L.obg_batch_create(None, 0, 0, None, C.byref(out)) == -1
