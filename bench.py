@@ -31,7 +31,8 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="plain1080",
-                   choices=["plain1080", "region4k", "small"])
+                   choices=["plain1080", "region4k", "small", "batched"])
+    p.add_argument("--streams", type=int, default=64, help="streams of the batched workload")
     p.add_argument("--n-test", type=int, default=None, help="override the number of test frames")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-test", type=int, default=900,
@@ -102,12 +103,134 @@ def cpu_baseline(host_train, host_test, spec, depth, num, den, region):
                       f"{dt:.1f} s single-threaded"}
 
 
+def run_batched(a):
+    """64 streams of mixed resolution, depth, T and threshold: the batched form
+    (one persistent launch per step, graph-captured, autotuned) against the
+    plain form (one launch per stream and frame) and one launch per stream."""
+    import ctypes
+    import torch
+    from paper_1412_1945_amd import obg
+    from synth import frames as S
+    from synth.fast import make_frames_gpu
+    obg.load()
+    L = obg.load()
+    wl = S.cfg3(n_streams=a.streams)
+    streams = []
+    print(f"# generating {len(wl.streams)} streams on the GPU", file=sys.stderr, flush=True)
+    for spec, d, thr in zip(wl.streams, wl.depth, wl.thr):
+        g = obg.FrameGeom(spec.width, spec.height, d)
+        fr = torch.empty((spec.n_frames, spec.height, spec.row_pitch), dtype=torch.uint8, device="cuda")
+        make_frames_gpu(spec, range(spec.n_frames), fr)
+        T, N = spec.n_train, spec.n_test
+        streams.append({"geom": g, "train": fr[:T], "n_train": T, "thr": thr, "test": fr[T:], "n_test": N,
+                        "occ": obg.empty_occ(g, T), "leafset": obg.empty_leafset(g),
+                        "mask": obg.empty_mask(g, N), "frames": fr,
+                        "p_occ": obg.empty_occ(g, T), "p_leaf": obg.empty_leafset(g), "p_mask": obg.empty_mask(g, N)})
+    torch.cuda.synchronize()
+    px_train = sum(s["n_train"] * s["geom"].width * s["geom"].height for s in streams)
+    px_test = sum(s["n_test"] * s["geom"].width * s["geom"].height for s in streams)
+    px = px_train + px_test
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    hs = ctypes.c_void_p(stream.cuda_stream)
+
+    print("# batch create (autotune)", file=sys.stderr, flush=True)
+    batch = obg.obg_batch_create(streams, flags=obg.BATCH_AUTOTUNE)
+    info = batch.info()
+    for _ in range(a.warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(a.steps):
+        batch.run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1) / a.steps
+
+    # plain: one call per stream and frame, raw C calls with prepared arguments
+    calls = []
+    for s in streams:
+        g = s["geom"]
+        gc = g.c()
+        fp = g.frame_pitch
+        tr, te = s["train"].data_ptr(), s["test"].data_ptr()
+        ow = g.words * 4
+        mw = g.height * g.mask_row_words * 8
+        calls.append((gc, tr, te, fp, s["p_occ"].data_ptr(), ow, s["p_leaf"].data_ptr(), s["p_mask"].data_ptr(),
+                      mw, s["n_train"], s["n_test"], s["thr"]))
+
+    def plain_per_frame():
+        for gc, tr, te, fp, occ, ow, leaf, mask, mw, T, N, (num, den) in calls:
+            gr = ctypes.byref(gc)
+            for f in range(T):
+                L.obg_train_frame(gr, tr + f * fp, 1, occ + f * ow, None, hs)
+            L.obg_merge(gr, occ, T, 0, T, num, den, leaf, hs)
+            for f in range(N):
+                L.obg_classify(gr, te + f * fp, 1, leaf, mask + f * mw, None, hs)
+
+    def plain_per_stream():
+        for gc, tr, te, fp, occ, ow, leaf, mask, mw, T, N, (num, den) in calls:
+            gr = ctypes.byref(gc)
+            L.obg_train_frame(gr, tr, T, occ, None, hs)
+            L.obg_merge(gr, occ, T, 0, T, num, den, leaf, hs)
+            L.obg_classify(gr, te, N, leaf, mask, None, hs)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, (time.perf_counter() - t0) * 1e3 / reps
+
+    print("# plain per frame", file=sys.stderr, flush=True)
+    ms_plain, host_plain = timed(plain_per_frame, 2)
+    same = all(torch.equal(s["occ"], s["p_occ"]) and torch.equal(s["leafset"], s["p_leaf"])
+               and torch.equal(s["mask"], s["p_mask"]) for s in streams)
+    print("# plain per stream", file=sys.stderr, flush=True)
+    ms_stream, _ = timed(plain_per_stream, 3)
+    same2 = all(torch.equal(s["mask"], s["p_mask"]) for s in streams)
+    bytes_step = 3 * px + px_test // 8
+    out = {
+        "metric": "train+classify Gpixel/s (batched)",
+        "value": round(px / (ms_batched * 1e-3) / 1e9, 3),
+        "unit": "Gpixel/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": round(ms_batched, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": wl.name, "streams": len(streams), "train_gpx": round(px_train / 1e9, 3),
+                   "test_gpx": round(px_test / 1e9, 3)},
+        "batched": {"ms": round(ms_batched, 3), "gpixel_s": round(px / (ms_batched * 1e-3) / 1e9, 1),
+                    "info": info},
+        "plain_per_frame": {"ms": round(ms_plain, 3), "host_ms": round(host_plain, 3),
+                            "gpixel_s": round(px / (ms_plain * 1e-3) / 1e9, 1),
+                            "launches": sum(c[9] + c[10] + 1 for c in calls)},
+        "plain_per_stream": {"ms": round(ms_stream, 3), "gpixel_s": round(px / (ms_stream * 1e-3) / 1e9, 1)},
+        "batched_vs_plain": round(ms_plain / ms_batched, 2),
+        "batched_vs_per_stream": round(ms_stream / ms_batched, 2),
+        "bit_exact_vs_plain": bool(same and same2),
+        "roofline": {"bound": "hbm", "achieved": round(bytes_step / (ms_batched * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(bytes_step / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "whole batch (train + merge + classify)"},
+    }
+    batch.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
+    if a.workload == "batched":
+        return run_batched(a)
     import torch
     from paper_1412_1945_amd import obg
     from synth.frames import make_frames
