@@ -160,7 +160,7 @@ def run_batched(a):
         calls.append((gc, tr, te, fp, s["p_occ"].data_ptr(), ow, s["p_leaf"].data_ptr(), s["p_mask"].data_ptr(),
                       mw, s["n_train"], s["n_test"], s["thr"]))
 
-    def plain_per_frame():
+    def plain_per_frame(hs=hs):
         for gc, tr, te, fp, occ, ow, leaf, mask, mw, T, N, (num, den) in calls:
             gr = ctypes.byref(gc)
             for f in range(T):
@@ -191,6 +191,16 @@ def run_batched(a):
     ms_plain, host_plain = timed(plain_per_frame, 2)
     same = all(torch.equal(s["occ"], s["p_occ"]) and torch.equal(s["leafset"], s["p_leaf"])
                and torch.equal(s["mask"], s["p_mask"]) for s in streams)
+    # the same per-frame launches replayed from a captured graph: no host
+    # overhead left, only the GPU time of one kernel per frame
+    print("# plain per frame, graph-replayed", file=sys.stderr, flush=True)
+    gph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(gph):
+        plain_per_frame(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    ms_plain_graph, _ = timed(gph.replay, 3)
+    same3 = all(torch.equal(s["mask"], s["p_mask"]) and torch.equal(s["leafset"], s["p_leaf"]) for s in streams)
+    del gph
     print("# plain per stream", file=sys.stderr, flush=True)
     ms_stream, _ = timed(plain_per_stream, 3)
     same2 = all(torch.equal(s["mask"], s["p_mask"]) for s in streams)
@@ -210,10 +220,13 @@ def run_batched(a):
         "plain_per_frame": {"ms": round(ms_plain, 3), "host_ms": round(host_plain, 3),
                             "gpixel_s": round(px / (ms_plain * 1e-3) / 1e9, 1),
                             "launches": sum(c[9] + c[10] + 1 for c in calls)},
+        "plain_per_frame_graph": {"ms": round(ms_plain_graph, 3),
+                                  "gpixel_s": round(px / (ms_plain_graph * 1e-3) / 1e9, 1)},
         "plain_per_stream": {"ms": round(ms_stream, 3), "gpixel_s": round(px / (ms_stream * 1e-3) / 1e9, 1)},
         "batched_vs_plain": round(ms_plain / ms_batched, 2),
+        "batched_vs_plain_graph": round(ms_plain_graph / ms_batched, 2),
         "batched_vs_per_stream": round(ms_stream / ms_batched, 2),
-        "bit_exact_vs_plain": bool(same and same2),
+        "bit_exact_vs_plain": bool(same and same2 and same3),
         "roofline": {"bound": "hbm", "achieved": round(bytes_step / (ms_batched * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(bytes_step / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
