@@ -186,6 +186,79 @@ int obg_batch_info_get(const obg_batch *batch, obg_batch_info *out);
 void obg_batch_destroy(obg_batch *batch);
 
 /*
+ * Serving: continuous batching of frames that arrive from many cameras.
+ *
+ * obg_serve_run drives one run to completion.  Frame f of stream s arrives
+ * at arrivals[s][f] simulated seconds (increasing per stream); simulated time
+ * runs `speed` times faster than wall time.  The loop admits arrived frames
+ * as long as the HBM budget (one arena: every stream's ring and leaf set,
+ * plus the buffers of the frames in flight) allows, forms a batch from the
+ * frames of many streams and enqueues it on one of `max_inflight` HIP
+ * streams, so that batches overlap on the device while new frames keep
+ * arriving.  A batch is: the ingest callback (writes the frames' pixels),
+ * the trees of training frames into ring slots, one pass over test frames
+ * that writes each mask and each frame's tree, and the merges that are due.
+ *   Frames 0 .. n_train-1 of a stream are training frames; after the last
+ *   one the model is the merge of all of them (Algorithm 2).  Frame f >=
+ *   n_train is test frame t = f - n_train; after every `remerge_period`-th
+ *   test frame the model becomes the merge of the last `remerge_window`
+ *   frames' trees (same threshold), used from the next frame on (a reading
+ *   of the paper's "octree updation", which gives no procedure).
+ *   Per stream, results do not depend on what else is in the mix.
+ * Latency of a test frame = time its mask is complete in HBM minus its
+ * arrival (wall clock).  Outputs for checking: per-frame mask checksums
+ * (a 64-bit hash of the mask words, `checksums[s * checksum_stride + f]`,
+ * NULL = off) and the full masks of the test frames of `watch_streams` copied
+ * to host buffers (watch_masks[w], [watch_max_frames][height][ceil(width/64)]).
+ * Streams: plain geometry, depth 1..6; pixels are packed RGB8 with row pitch
+ * 3*width rounded up to 16 bytes.
+ */
+typedef struct obg_ingest_item {
+    int32_t stream;
+    int32_t frame;
+    uint8_t *dst;        /* device buffer of height * row_pitch bytes */
+} obg_ingest_item;
+
+/* Enqueue the writing of the items' pixels on `stream`; 0 = success. */
+typedef int (*obg_ingest_fn)(void *ctx, const obg_ingest_item *items, int32_t n, hipStream_t stream);
+
+typedef struct obg_serve_stream {
+    int32_t width, height, depth;
+    int32_t n_train;
+    uint32_t thr_num, thr_den;
+} obg_serve_stream;
+
+typedef struct obg_serve_config {
+    const obg_serve_stream *streams;
+    int32_t n_streams;
+    const double *const *arrivals;     /* [n_streams][n_arrivals[s]] simulated seconds */
+    const int32_t *n_arrivals;
+    double speed;                      /* simulated seconds per wall second, > 0 */
+    uint64_t budget_bytes;
+    int32_t max_inflight;              /* 1..16 batches on the device at once */
+    int32_t max_batch_frames;          /* 1..4096 */
+    int32_t remerge_period, remerge_window;   /* 1 <= window <= period */
+    obg_ingest_fn ingest;
+    void *ingest_ctx;
+    uint64_t *checksums;               /* NULLABLE */
+    int32_t checksum_stride;
+    const int32_t *watch_streams;      /* NULLABLE */
+    int32_t n_watch;
+    uint64_t *const *watch_masks;
+    int32_t watch_max_frames;
+} obg_serve_config;
+
+typedef struct obg_serve_stats {
+    int64_t frames_arrived, frames_served, train_frames, test_frames, pixels;
+    int64_t batches, merges, admission_waits;
+    double wall_s;
+    double lat_p50_ms, lat_p99_ms, lat_max_ms, lat_mean_ms;
+    double peak_bytes;                 /* arena bytes in use at the peak */
+} obg_serve_stats;
+
+int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
+
+/*
  * Launch-shape knobs of the pixel kernels, process-wide, for the autotuner
  * (0 restores the built-in default).  They change speed only: every setting
  * gives the same bytes.

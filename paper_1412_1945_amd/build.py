@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libobg.so")
-SOURCES = ["kernels.hip", "api.hip", "probe.hip", "batch.hip"]
+SOURCES = ["kernels.hip", "api.hip", "probe.hip", "batch.hip", "serve.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

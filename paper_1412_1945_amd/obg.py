@@ -59,6 +59,37 @@ class BatchInfo(ctypes.Structure):
     ]
 
 
+class ServeStream(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("n_train", ctypes.c_int32), ("thr_num", ctypes.c_uint32), ("thr_den", ctypes.c_uint32)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [
+        ("streams", ctypes.POINTER(ServeStream)), ("n_streams", ctypes.c_int32),
+        ("arrivals", ctypes.POINTER(ctypes.POINTER(ctypes.c_double))),
+        ("n_arrivals", ctypes.POINTER(ctypes.c_int32)),
+        ("speed", ctypes.c_double), ("budget_bytes", ctypes.c_uint64),
+        ("max_inflight", ctypes.c_int32), ("max_batch_frames", ctypes.c_int32),
+        ("remerge_period", ctypes.c_int32), ("remerge_window", ctypes.c_int32),
+        ("ingest", ctypes.c_void_p), ("ingest_ctx", ctypes.c_void_p),
+        ("checksums", ctypes.POINTER(ctypes.c_uint64)), ("checksum_stride", ctypes.c_int32),
+        ("watch_streams", ctypes.POINTER(ctypes.c_int32)), ("n_watch", ctypes.c_int32),
+        ("watch_masks", ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64))), ("watch_max_frames", ctypes.c_int32),
+    ]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [
+        ("frames_arrived", ctypes.c_int64), ("frames_served", ctypes.c_int64),
+        ("train_frames", ctypes.c_int64), ("test_frames", ctypes.c_int64), ("pixels", ctypes.c_int64),
+        ("batches", ctypes.c_int64), ("merges", ctypes.c_int64), ("admission_waits", ctypes.c_int64),
+        ("wall_s", ctypes.c_double),
+        ("lat_p50_ms", ctypes.c_double), ("lat_p99_ms", ctypes.c_double), ("lat_max_ms", ctypes.c_double),
+        ("lat_mean_ms", ctypes.c_double), ("peak_bytes", ctypes.c_double),
+    ]
+
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -86,6 +117,7 @@ def load() -> ctypes.CDLL:
             "obg_batch_run": (ctypes.c_int, [P, P]),
             "obg_batch_info_get": (ctypes.c_int, [P, ctypes.POINTER(BatchInfo)]),
             "obg_batch_destroy": (None, [P]),
+            "obg_serve_run": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(ServeStats)]),
             "obg_last_error": (ctypes.c_char_p, []),
             "obg_version": (ctypes.c_char_p, []),
         }
@@ -101,7 +133,7 @@ def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
             "obg_merge", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_probe",
             "obg_batch_create", "obg_batch_run", "obg_batch_info_get", "obg_batch_destroy",
-            "obg_last_error", "obg_version"]
+            "obg_serve_run", "obg_last_error", "obg_version"]
 
 
 @dataclass
@@ -298,6 +330,54 @@ def obg_batch_create(streams, flags: int = 0, stream=None) -> Batch:
     h = ctypes.c_void_p()
     _check(load().obg_batch_create(arr, len(streams), flags, _stream(stream), ctypes.byref(h)))
     return Batch(h, keep)
+
+
+def obg_serve_run(streams, arrivals, ingest_fn: int, ingest_ctx: int, speed: float = 1.0,
+                  budget_bytes: int = 32 << 30, max_inflight: int = 3, max_batch_frames: int = 256,
+                  remerge_period: int = 100, remerge_window: int = 50, checksums=None,
+                  watch=None, watch_masks=None, watch_max_frames: int = 0) -> dict:
+    """streams: list of dicts (width, height, depth, n_train, thr=(num, den));
+    arrivals: list of float64 numpy arrays (seconds); checksums: optional uint64
+    numpy array [n_streams, stride]; watch: stream indices whose masks are
+    copied into watch_masks (uint64 numpy arrays [frames, H, ceil(W/64)])."""
+    import numpy as np
+    n = len(streams)
+    arr = (ServeStream * n)()
+    for i, s in enumerate(streams):
+        arr[i] = ServeStream(s["width"], s["height"], s["depth"], s["n_train"], s["thr"][0], s["thr"][1])
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in arrivals]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
+    counts = (ctypes.c_int32 * n)(*[len(a) for a in arrs])
+    cfg = ServeConfig()
+    cfg.streams = arr
+    cfg.n_streams = n
+    cfg.arrivals = ptrs
+    cfg.n_arrivals = counts
+    cfg.speed = speed
+    cfg.budget_bytes = budget_bytes
+    cfg.max_inflight = max_inflight
+    cfg.max_batch_frames = max_batch_frames
+    cfg.remerge_period = remerge_period
+    cfg.remerge_window = remerge_window
+    cfg.ingest = ingest_fn
+    cfg.ingest_ctx = ingest_ctx
+    if checksums is not None:
+        assert checksums.dtype == np.uint64 and checksums.flags.c_contiguous and checksums.shape[0] == n
+        cfg.checksums = checksums.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        cfg.checksum_stride = checksums.shape[1]
+    keep = []
+    if watch:
+        ws = (ctypes.c_int32 * len(watch))(*watch)
+        wm = (ctypes.POINTER(ctypes.c_uint64) * len(watch))(
+            *[m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)) for m in watch_masks])
+        keep += [ws, wm]
+        cfg.watch_streams = ws
+        cfg.n_watch = len(watch)
+        cfg.watch_masks = wm
+        cfg.watch_max_frames = watch_max_frames
+    st = ServeStats()
+    _check(load().obg_serve_run(ctypes.byref(cfg), ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in ServeStats._fields_}
 
 
 def obg_version() -> str:

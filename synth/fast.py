@@ -97,3 +97,68 @@ def make_frames_gpu(spec: F.StreamSpec, frames: Sequence[int], out: torch.Tensor
         # recs must outlive the kernel: wait before the next chunk reuses memory
         s.synchronize()
     return out
+
+
+def poisson_arrivals(rates, duration_s: float, seed: int):
+    """Per stream: increasing arrival times (seconds) of a Poisson process."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    out = []
+    for lam in rates:
+        n_max = int(lam * duration_s * 1.5 + 50)
+        gaps = rng.exponential(1.0 / lam, size=n_max)
+        t = np.cumsum(gaps)
+        while t[-1] < duration_s:
+            t = np.concatenate([t, t[-1] + np.cumsum(rng.exponential(1.0 / lam, size=n_max))])
+        out.append(np.ascontiguousarray(t[t < duration_s], dtype=np.float64))
+    return out
+
+
+class IngestContext:
+    """Frame source of a serving run: frame f of stream s is frame f of the
+    stream's synthetic sequence, written on the GPU when the server asks."""
+
+    def __init__(self, specs, n_frames, slots: int, device="cuda"):
+        lib = _load()
+        P = ctypes.c_void_p
+        lib.synth_ingest_create.restype = ctypes.c_void_p
+        lib.synth_ingest_create.argtypes = [ctypes.c_int32, P, P, P, P, P, ctypes.c_int32]
+        lib.synth_ingest_destroy.restype = None
+        lib.synth_ingest_destroy.argtypes = [P]
+        self.lib = lib
+        params, recs, base, counts = [], [], [], []
+        total = 0
+        for spec, n in zip(specs, n_frames):
+            sk = F._stream_key(spec)
+            params += [spec.width, spec.height, spec.row_pitch, F.fmix32(sk ^ F._P_PALETTE),
+                       F.fmix32(sk ^ F._P_BIMODAL), min(int(spec.bimodal_frac * 4294967296.0), 0xFFFFFFFF),
+                       1 if spec.bimodal_frac > 0 else 0, spec.bimodal_period, spec.block, spec.n_palette, 0, 0]
+            recs.append(frame_records(spec, range(max(n, 1))))
+            base.append(total)
+            counts.append(n)
+            total += max(n, 1)
+        p64 = torch.tensor(params, dtype=torch.int64)
+        self.params = torch.where(p64 >= 2 ** 31, p64 - 2 ** 32, p64).to(torch.int32).contiguous()
+        self.recs = torch.cat(recs).to(device).contiguous()
+        self.base = torch.tensor(base, dtype=torch.int64).contiguous()
+        self.counts = torch.tensor(counts, dtype=torch.int32).contiguous()
+        sigma = specs[0].noise_sigma
+        assert all(s.noise_sigma == sigma for s in specs)
+        self.ntab = torch.tensor(F.noise_table(sigma), dtype=torch.int16, device=device)
+        self.ctx = lib.synth_ingest_create(len(specs), self.params.data_ptr(), self.recs.data_ptr(),
+                                           self.base.data_ptr(), self.counts.data_ptr(), self.ntab.data_ptr(),
+                                           slots)
+        if not self.ctx:
+            raise RuntimeError("synth_ingest_create failed")
+        self.fn = ctypes.cast(lib.synth_ingest, ctypes.c_void_p).value
+
+    def close(self):
+        if self.ctx:
+            self.lib.synth_ingest_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

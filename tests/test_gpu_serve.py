@@ -1,0 +1,115 @@
+"""Serving: continuous batching with rolling re-merge.
+
+Each result must be the oracle's, and the same whether a stream is served
+alone, in the mix, or under a budget that makes frames wait for admission.
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+PERIOD, WINDOW = 10, 5
+
+
+@pytest.fixture(scope="module")
+def env(oracle_lib):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1412_1945_amd import obg
+    obg.load()
+    return obg, oracle_lib
+
+
+def _setup():
+    from synth.frames import StreamSpec
+    from synth.fast import poisson_arrivals
+    shapes = [(64, 32, 3, 5, (1, 2)), (96, 40, 4, 6, (3, 10)), (160, 24, 5, 4, (7, 10)),
+              (33, 17, 6, 7, (1, 2)), (128, 64, 5, 8, (1, 1))]
+    specs, streams = [], []
+    for i, (W, H, d, T, thr) in enumerate(shapes):
+        specs.append(StreamSpec(W, H, T, 400, seed=21, stream=i, fg="ellipses", fg_coverage=0.15,
+                                bimodal_frac=0.2, drift_amp=0.2, drift_period=40))
+        streams.append({"width": W, "height": H, "depth": d, "n_train": T, "thr": thr})
+    arrivals = poisson_arrivals([300.0] * len(specs), 0.5, seed=7)
+    return specs, streams, arrivals
+
+
+def _serve(obg, specs, streams, arrivals, which, budget=1 << 30, watch=(), speed=1.0):
+    from synth.fast import IngestContext
+    sp = [specs[i] for i in which]
+    st = [streams[i] for i in which]
+    ar = [arrivals[i] for i in which]
+    ctx = IngestContext(sp, [len(a) for a in ar], slots=4)
+    stride = max(len(a) for a in ar)
+    sums = np.zeros((len(which), stride), dtype=np.uint64)
+    wl = [which.index(w) for w in watch]
+    masks = [np.zeros((len(ar[j]), st[j]["height"], (st[j]["width"] + 63) // 64), dtype=np.uint64) for j in wl]
+    stats = obg.obg_serve_run(st, ar, ctx.fn, ctx.ctx, speed=speed, budget_bytes=budget, max_inflight=3,
+                              max_batch_frames=64, remerge_period=PERIOD, remerge_window=WINDOW,
+                              checksums=sums, watch=wl, watch_masks=masks,
+                              watch_max_frames=max((m.shape[0] for m in masks), default=0))
+    ctx.close()
+    return stats, sums, masks
+
+
+def _oracle_masks(O, spec, stream, n_frames):
+    from synth.frames import make_frames
+    T, (num, den) = stream["n_train"], stream["thr"]
+    frames = make_frames(spec, range(n_frames), device="cpu").numpy()
+    f = O.Forest(spec.width, spec.height, stream["depth"])
+    model = f.merge(f.add_frames(list(frames[:T])), num, den)
+    trees, out = {}, []
+    for t in range(n_frames - T):
+        k = T + t
+        out.append(model.classify(frames[k]))
+        trees[k] = f.add_frame(frames[k])
+        if (t + 1) % PERIOD == 0:
+            model = f.merge([trees[k - WINDOW + 1 + j] for j in range(WINDOW)], num, den)
+            for j in [i for i in trees if i <= k - WINDOW]:
+                f.drop(trees.pop(j))
+    return out
+
+
+def test_serve_matches_oracle_and_alone(env):
+    obg, O = env
+    specs, streams, arrivals = _setup()
+    every = list(range(len(specs)))
+    print(f"[case] serve mix of {len(specs)} streams, {sum(len(a) for a in arrivals)} frames", flush=True)
+    stats, sums, masks = _serve(obg, specs, streams, arrivals, every, watch=(1, 3))
+    assert stats["frames_served"] == stats["frames_arrived"] == sum(len(a) for a in arrivals)
+    assert stats["merges"] >= len(specs) * 5
+    assert stats["batches"] > 1
+    for w, m in zip((1, 3), masks):
+        T = streams[w]["n_train"]
+        want = _oracle_masks(O, specs[w], streams[w], len(arrivals[w]))
+        got = m[: len(arrivals[w]) - T]
+        assert len(want) == len(got)
+        for t in range(len(want)):
+            assert np.array_equal(got[t], want[t]), f"stream {w} test frame {t}"
+    for w in (0, 2, 4):
+        print(f"[case] serve stream {w} alone", flush=True)
+        _, alone, _ = _serve(obg, specs, streams, arrivals, [w])
+        n = len(arrivals[w])
+        T = streams[w]["n_train"]
+        assert np.array_equal(alone[0, T:n], sums[w, T:n]), f"stream {w}: alone differs from the mix"
+        assert np.count_nonzero(sums[w, T:n]) > 0
+
+
+def test_serve_tight_budget_same_results(env):
+    obg, O = env
+    specs, streams, arrivals = _setup()
+    every = list(range(len(specs)))
+    _, ref, _ = _serve(obg, specs, streams, arrivals, every)
+    # rings and leaf sets of all streams, plus room for about three frames
+    state = 0
+    for s in streams:
+        words = max(1, (1 << (3 * s["depth"])) // 32)
+        ring = max(s["n_train"], WINDOW)
+        state += ((ring * words * 4 + 255) // 256) * 256 + ((words * 4 + 255) // 256) * 256
+    frame = ((64 * 384 + 255) // 256) * 256 + 1024      # largest frame and its mask
+    print(f"[case] serve with budget {state + 3 * frame}", flush=True)
+    stats, sums, _ = _serve(obg, specs, streams, arrivals, every, budget=state + 3 * frame, speed=4.0)
+    assert stats["admission_waits"] > 0
+    assert stats["frames_served"] == stats["frames_arrived"]
+    assert np.array_equal(sums, ref)
