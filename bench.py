@@ -31,9 +31,14 @@ def parse():
     p.add_argument("--steps", type=int, default=50)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", default="plain1080",
-                   choices=["plain1080", "region4k", "small", "batched"])
+                   choices=["plain1080", "region4k", "small", "batched", "served"])
     p.add_argument("--streams", type=int, default=64, help="streams of the batched workload")
     p.add_argument("--n-test", type=int, default=None, help="override the number of test frames")
+    p.add_argument("--serve-seconds", type=float, default=60.0,
+                   help="simulated seconds of arrivals in the real-time served run")
+    p.add_argument("--serve-capacity-seconds", type=float, default=10.0,
+                   help="seconds of arrivals offered all at once to measure the served capacity")
+    p.add_argument("--serve-budget-gib", type=float, default=32.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-sample-test", type=int, default=900,
                    help="test frames in the oracle's timed sample")
@@ -236,6 +241,150 @@ def run_batched(a):
     print(json.dumps(out), flush=True)
 
 
+def oracle_served_replay(spec, depth, T, num, den, n_frames, period, window, budget_s):
+    """The oracle on one served stream: model from frames 0..T-1, then each
+    test frame is classified and kept as a tree; every `period` test frames the
+    model is re-merged from the trees of the last `window` frames.  Stops
+    after the first test frame that ends past `budget_s` seconds."""
+    from oracle import octree
+    from synth.frames import make_frames
+    t0 = time.perf_counter()
+    f = octree.Forest(spec.width, spec.height, depth)
+    train = make_frames(spec, range(T), device="cpu").numpy()
+    model = f.merge(f.add_frames(list(train)), num, den)
+    trees, masks = {}, []
+    for k in range(T, n_frames):
+        fr = make_frames(spec, [k], device="cpu").numpy()[0]
+        masks.append(model.classify(fr))
+        trees[k] = f.add_frame(fr)
+        t = k - T
+        if (t + 1) % period == 0:
+            model = f.merge([trees[k - window + 1 + j] for j in range(window)], num, den)
+        for j in [i for i in trees if i <= k - window]:
+            f.drop(trees.pop(j))
+        if time.perf_counter() - t0 > budget_s:
+            break
+    return masks, time.perf_counter() - t0
+
+
+def run_served(a):
+    """Serving: 256 streams of the mixed workload, Poisson arrivals at 5-30 fps
+    each, frames written into HBM by the synthetic source when admitted,
+    continuous batching under a 32 GiB budget, re-merge every 100 test frames
+    over the last 50.  Two runs: real time (latency at the offered load) and
+    every frame offered at once (capacity)."""
+    import numpy as np
+    import torch
+    from paper_1412_1945_amd import obg
+    from synth import frames as S
+    from synth.fast import IngestContext, poisson_arrivals
+    obg.load()
+    specs, depths, thrs, rates = S.cfg4()
+    period, window = 100, 50
+    arrivals = poisson_arrivals(rates, a.serve_seconds, seed=4)
+    streams = [{"width": sp.width, "height": sp.height, "depth": d, "n_train": sp.n_train, "thr": thr}
+               for sp, d, thr in zip(specs, depths, thrs)]
+    n_frames = [len(x) for x in arrivals]
+    # watched stream: the first smallest one, its masks kept for the oracle sample
+    small = min(range(len(specs)), key=lambda i: (specs[i].width * specs[i].height, i))
+    wmax = n_frames[small] - specs[small].n_train
+    print(f"# served: {len(specs)} streams, {sum(n_frames)} frames over {a.serve_seconds} s; "
+          f"building the frame source", file=sys.stderr, flush=True)
+    ctx = IngestContext(specs, n_frames, slots=8)
+    budget = int(a.serve_budget_gib * (1 << 30))
+    stride = max(n_frames)
+
+    def serve(arr, speed, watch):
+        sums = np.zeros((len(specs), stride), dtype=np.uint64)
+        masks = ([np.zeros((wmax, specs[small].height, (specs[small].width + 63) // 64), dtype=np.uint64)]
+                 if watch else [])
+        st = obg.obg_serve_run(streams, arr, ctx.fn, ctx.ctx, speed=speed, budget_bytes=budget,
+                               max_inflight=3, max_batch_frames=256, remerge_period=period,
+                               remerge_window=window, checksums=sums,
+                               watch=[small] if watch else None, watch_masks=masks,
+                               watch_max_frames=wmax if watch else 0)
+        return st, sums, masks
+
+    # warm-up: one second of arrivals, offered at once
+    serve([x[x < 1.0] for x in arrivals], 1e9, False)
+    print("# served capacity run", file=sys.stderr, flush=True)
+    cap_arr = [x[x < a.serve_capacity_seconds] for x in arrivals]
+    cap, cap_sums, _ = serve(cap_arr, 1e9, False)
+    print(f"# served real-time run ({a.serve_seconds} s)", file=sys.stderr, flush=True)
+    rt, rt_sums, wmasks = serve(arrivals, 1.0, True)
+    ctx.close()
+    # frames served in both runs give the same masks
+    same = all(np.array_equal(cap_sums[s, :len(cap_arr[s])], rt_sums[s, :len(cap_arr[s])])
+               for s in range(len(specs)))
+
+    def path_bytes(arr):
+        b = 0
+        for sp, d, x in zip(specs, depths, arr):
+            n, T = len(x), sp.n_train
+            words_b = max(4, (1 << (3 * d)) // 8)
+            px = sp.width * sp.height
+            n_test = max(n - T, 0)
+            b += n * (3 * px + words_b) + n_test * (sp.height * ((sp.width + 63) // 64) * 8 + words_b)
+            merges = (1 if n >= T else 0) + n_test // period
+            b += merges * words_b * (window + 1)
+        return b
+
+    cap_px = cap["train_pixels"] + cap["test_pixels"]
+    rt_px = rt["train_pixels"] + rt["test_pixels"]
+    cap_bytes = path_bytes(cap_arr)
+    achieved = cap_bytes / cap["path_busy_s"] / 1e9
+    out = {
+        "metric": "train+classify Gpixel/s (served), p50/p99 frame latency",
+        "value": round(cap_px / cap["wall_s"] / 1e9, 3),
+        "unit": "Gpixel/s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": round(cap["wall_s"] * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u8", "data": "synthetic",
+        "config": {"workload": f"served-{len(specs)}-streams-mixed", "streams": len(specs),
+                   "fps_range": [5, 30], "offered_gpixel_s": round(sum(r * sp.width * sp.height for r, sp in
+                                                                       zip(rates, specs)) / 1e9, 3),
+                   "budget_gib": a.serve_budget_gib, "remerge_period": period, "remerge_window": window,
+                   "max_inflight_batches": 3, "max_batch_frames": 256},
+        "capacity": {"simulated_s": a.serve_capacity_seconds, "frames": cap["frames_served"],
+                     "gpixel": round(cap_px / 1e9, 2), "wall_s": round(cap["wall_s"], 3),
+                     "gpixel_s": round(cap_px / cap["wall_s"] / 1e9, 2),
+                     "device_busy_s": round(cap["busy_s"], 3), "path_busy_s": round(cap["path_busy_s"], 3),
+                     "path_gpixel_s": round(cap_px / cap["path_busy_s"] / 1e9, 2),
+                     "batches": cap["batches"], "merges": cap["merges"],
+                     "peak_gib": round(cap["peak_bytes"] / 2 ** 30, 2),
+                     "admission_waits": cap["admission_waits"]},
+        "realtime": {"simulated_s": a.serve_seconds, "frames": rt["frames_served"],
+                     "gpixel": round(rt_px / 1e9, 2), "wall_s": round(rt["wall_s"], 3),
+                     "gpixel_s": round(rt_px / rt["wall_s"] / 1e9, 3),
+                     "lat_p50_ms": round(rt["lat_p50_ms"], 3), "lat_p99_ms": round(rt["lat_p99_ms"], 3),
+                     "lat_max_ms": round(rt["lat_max_ms"], 3), "lat_mean_ms": round(rt["lat_mean_ms"], 3),
+                     "batches": rt["batches"], "merges": rt["merges"],
+                     "device_busy_frac": round(rt["busy_s"] / rt["wall_s"], 4),
+                     "peak_gib": round(rt["peak_bytes"] / 2 ** 30, 2),
+                     "admission_waits": rt["admission_waits"]},
+        "capacity_vs_realtime_identical": bool(same),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "served path (fused classify+occupancy, occupancy, merge) while batches "
+                               "overlap with the frame source",
+                     "bytes": cap_bytes},
+    }
+    if not a.no_cpu_baseline:
+        print("# cpu baseline (oracle replay of the watched stream)", file=sys.stderr, flush=True)
+        sp = specs[small]
+        got, dt = oracle_served_replay(sp, depths[small], sp.n_train, *thrs[small], n_frames[small],
+                                       period, window, budget_s=15.0)
+        ok = all(np.array_equal(wmasks[0][i], got[i]) for i in range(len(got)))
+        px = (sp.n_train + len(got)) * sp.width * sp.height
+        out["cpu_baseline"] = {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+                               "sample": f"stream {small} ({sp.width}x{sp.height}, d={depths[small]}): "
+                                         f"{sp.n_train} training frames and the first {len(got)} served test "
+                                         f"frames with re-merges, {dt:.1f} s single-threaded",
+                               "masks_equal_served": bool(ok)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -244,6 +393,8 @@ def main():
         sys.exit(2)
     if a.workload == "batched":
         return run_batched(a)
+    if a.workload == "served":
+        return run_served(a)
     import torch
     from paper_1412_1945_amd import obg
     from synth.frames import make_frames

@@ -254,6 +254,12 @@ typedef struct obg_serve_stats {
     double wall_s;
     double lat_p50_ms, lat_p99_ms, lat_max_ms, lat_mean_ms;
     double peak_bytes;                 /* arena bytes in use at the peak */
+    int64_t train_pixels, test_pixels;
+    /* seconds during which at least one batch was on the device: from its
+       first copy to its completion (busy_s), and only its path kernels, from
+       the end of ingest to the end of its merges (path_busy_s); overlapping
+       batches count once */
+    double busy_s, path_busy_s;
 } obg_serve_stats;
 
 int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);

@@ -276,8 +276,8 @@ hipError_t enqueue(obg_batch *b, hipStream_t st) {
 }
 
 void drop_graph(obg_batch *b) {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
 }
@@ -326,16 +326,16 @@ int time_shape(obg_batch *b, hipStream_t st, float *ms) {
     rc = run_once(b, st);  // warm-up
     float best = 1e30f;
     for (int r = 0; r < 3 && rc == OBG_OK; ++r) {
-        hipEventRecord(e0, st);
+        (void)hipEventRecord(e0, st);
         rc = run_once(b, st);
-        hipEventRecord(e1, st);
+        (void)hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess) rc = bfail(OBG_EHIP, "timing sync");
         float t = 0;
-        hipEventElapsedTime(&t, e0, e1);
+        (void)hipEventElapsedTime(&t, e0, e1);
         best = std::min(best, t);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     *ms = best;
     return rc;
 }
@@ -391,9 +391,9 @@ int autotune(obg_batch *b, hipStream_t st) {
 void destroy(obg_batch *b) {
     if (!b) return;
     drop_graph(b);
-    if (b->cap) hipStreamDestroy(b->cap);
-    if (b->d) hipFree(b->d);
-    if (b->d_sum) hipFree(b->d_sum);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->d) (void)hipFree(b->d);
+    if (b->d_sum) (void)hipFree(b->d_sum);
     delete b;
 }
 

@@ -219,7 +219,7 @@ struct PendingFrame {
 
 struct Slot {
     hipStream_t st = nullptr;
-    hipEvent_t done = nullptr;
+    hipEvent_t done = nullptr, start = nullptr, k0 = nullptr, k1 = nullptr;
     bool busy = false;
     std::vector<PendingFrame> frames;
     std::vector<int> merge_streams;
@@ -230,6 +230,23 @@ struct Slot {
 };
 
 int sfail(int code, const char *msg) { return set_error(code, msg); }
+
+// total length covered by a set of [begin, end] intervals
+double union_length(std::vector<std::pair<double, double>> iv) {
+    std::sort(iv.begin(), iv.end());
+    double total = 0, b = 0, e = -1;
+    for (auto &p : iv) {
+        if (p.first > e) {
+            if (e > b) total += e - b;
+            b = p.first;
+            e = p.second;
+        } else if (p.second > e) {
+            e = p.second;
+        }
+    }
+    if (e > b) total += e - b;
+    return total;
+}
 
 void fill_frame(ServeFrameDev &fd, const StreamState &ss, const uint8_t *rgb, uint32_t *occ, uint64_t *mask,
                 int span_target) {
@@ -325,7 +342,8 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     const int maxf = cfg->max_batch_frames;
     for (auto &sl : slots) {
         if (hipStreamCreateWithFlags(&sl.st, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreate(&sl.done) != hipSuccess ||
+            hipEventCreate(&sl.done) != hipSuccess || hipEventCreate(&sl.start) != hipSuccess ||
+            hipEventCreate(&sl.k0) != hipSuccess || hipEventCreate(&sl.k1) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_frames, sizeof(ServeFrameDev) * maxf * 2, hipHostMallocDefault) != hipSuccess ||
             hipMalloc((void **)&sl.d_frames, sizeof(ServeFrameDev) * maxf * 2) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_jobs, sizeof(MergeJobDev) * ns, hipHostMallocDefault) != hipSuccess ||
@@ -353,12 +371,14 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     }
     std::vector<double> lat;
     lat.reserve(arr.size());
+    std::vector<std::pair<double, double>> busy_iv, path_iv;   // per batch, ms after t0
     size_t next_arr = 0;
     int64_t served = 0, admission_waits = 0, batches = 0, merges = 0, pixels = 0, train_frames = 0, test_frames = 0;
+    int64_t train_pixels = 0, test_pixels = 0;
     const Clock::time_point wall0 = Clock::now();
     if (rc == OBG_OK) {
-        hipEventRecord(t0, slots[0].st);
-        hipEventSynchronize(t0);
+        (void)hipEventRecord(t0, slots[0].st);
+        (void)hipEventSynchronize(t0);
     }
     const Clock::time_point start = Clock::now();
     auto wall_now = [&]() { return std::chrono::duration<double>(Clock::now() - start).count(); };
@@ -377,8 +397,13 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             hipError_t q = hipEventQuery(sl.done);
             if (q == hipErrorNotReady) continue;
             if (q != hipSuccess) { rc = sfail(OBG_EHIP, "batch failed on the device"); break; }
-            float ms = 0;
-            hipEventElapsedTime(&ms, t0, sl.done);
+            float ms = 0, ms_s = 0, ms_k0 = 0, ms_k1 = 0;
+            (void)hipEventElapsedTime(&ms, t0, sl.done);
+            (void)hipEventElapsedTime(&ms_s, t0, sl.start);
+            (void)hipEventElapsedTime(&ms_k0, t0, sl.k0);
+            (void)hipEventElapsedTime(&ms_k1, t0, sl.k1);
+            busy_iv.push_back({ms_s, ms});
+            path_iv.push_back({ms_k0, ms_k1});
             const double done_s = ms * 1e-3;
             int ti = 0;
             for (auto &pf : sl.frames) {
@@ -389,8 +414,10 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                         cfg->checksums[(int64_t)pf.stream * cfg->checksum_stride + pf.frame] = sl.h_sum[ti];
                     ++ti;
                     ++test_frames;
+                    test_pixels += (int64_t)ss.cfg.width * ss.cfg.height;
                 } else {
                     ++train_frames;
+                    train_pixels += (int64_t)ss.cfg.width * ss.cfg.height;
                 }
                 pixels += (int64_t)ss.cfg.width * ss.cfg.height;
                 arena.put(pf.rgb, ss.frame_bytes);
@@ -506,11 +533,13 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 }
                 for (int s : sl.merge_streams) S[s].merge_inflight = true;
                 hipStream_t st = sl.st;
-                bool ok = hipMemcpyAsync(sl.d_frames, sl.h_frames, sizeof(ServeFrameDev) * (nt + nc),
+                bool ok = hipEventRecord(sl.start, st) == hipSuccess;
+                if (ok) ok = hipMemcpyAsync(sl.d_frames, sl.h_frames, sizeof(ServeFrameDev) * (nt + nc),
                                          hipMemcpyHostToDevice, st) == hipSuccess;
                 if (ok && n_jobs)
                     ok = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, sizeof(MergeJobDev) * n_jobs, hipMemcpyHostToDevice, st) == hipSuccess;
                 if (ok) ok = cfg->ingest(cfg->ingest_ctx, sl.items, nt + nc, st) == 0;
+                if (ok) ok = hipEventRecord(sl.k0, st) == hipSuccess;
                 if (ok) {
                     hipLaunchKernelGGL(serve_zero_kernel, dim3(8, nt + nc), dim3(256), 0, st,
                                        (const ServeFrameDev *)sl.d_frames);
@@ -530,6 +559,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                         hipLaunchKernelGGL(serve_merge_kernel, dim3((maxw + 255) / 256, n_jobs), dim3(256), 0, st,
                                            (const MergeJobDev *)sl.d_jobs);
                     }
+                    if (ok) ok = hipEventRecord(sl.k1, st) == hipSuccess;
                     if (nc && cfg->checksums) {
                         ok = hipMemsetAsync(sl.d_sum, 0, sizeof(unsigned long long) * nc, st) == hipSuccess;
                         hipLaunchKernelGGL(serve_checksum_kernel, dim3(16, nc), dim3(256), 0, st,
@@ -578,7 +608,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     }
     const double wall = wall_now();
     for (auto &sl : slots)
-        if (sl.st) hipStreamSynchronize(sl.st);
+        if (sl.st) (void)hipStreamSynchronize(sl.st);
     std::sort(lat.begin(), lat.end());
     auto pct = [&](double p) -> double {
         if (lat.empty()) return 0.0;
@@ -602,19 +632,24 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     for (double v : lat) sum += v;
     stats->lat_mean_ms = lat.empty() ? 0.0 : sum / lat.size();
     stats->peak_bytes = (double)arena.peak;
+    stats->train_pixels = train_pixels;
+    stats->test_pixels = test_pixels;
+    stats->busy_s = union_length(busy_iv) * 1e-3;
+    stats->path_busy_s = union_length(path_iv) * 1e-3;
     (void)wall0;
     for (auto &sl : slots) {
-        if (sl.st) hipStreamDestroy(sl.st);
-        if (sl.done) hipEventDestroy(sl.done);
-        if (sl.h_frames) hipHostFree(sl.h_frames);
-        if (sl.d_frames) hipFree(sl.d_frames);
-        if (sl.h_jobs) hipHostFree(sl.h_jobs);
-        if (sl.d_jobs) hipFree(sl.d_jobs);
-        if (sl.h_sum) hipHostFree(sl.h_sum);
-        if (sl.d_sum) hipFree(sl.d_sum);
+        if (sl.st) (void)hipStreamDestroy(sl.st);
+        for (hipEvent_t ev : {sl.done, sl.start, sl.k0, sl.k1})
+            if (ev) (void)hipEventDestroy(ev);
+        if (sl.h_frames) (void)hipHostFree(sl.h_frames);
+        if (sl.d_frames) (void)hipFree(sl.d_frames);
+        if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
+        if (sl.d_jobs) (void)hipFree(sl.d_jobs);
+        if (sl.h_sum) (void)hipHostFree(sl.h_sum);
+        if (sl.d_sum) (void)hipFree(sl.d_sum);
         delete[] sl.items;
     }
-    if (t0) hipEventDestroy(t0);
-    hipFree(arena.base);
+    if (t0) (void)hipEventDestroy(t0);
+    (void)hipFree(arena.base);
     return rc;
 }

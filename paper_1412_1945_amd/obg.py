@@ -87,6 +87,8 @@ class ServeStats(ctypes.Structure):
         ("wall_s", ctypes.c_double),
         ("lat_p50_ms", ctypes.c_double), ("lat_p99_ms", ctypes.c_double), ("lat_max_ms", ctypes.c_double),
         ("lat_mean_ms", ctypes.c_double), ("peak_bytes", ctypes.c_double),
+        ("train_pixels", ctypes.c_int64), ("test_pixels", ctypes.c_int64),
+        ("busy_s", ctypes.c_double), ("path_busy_s", ctypes.c_double),
     ]
 
 

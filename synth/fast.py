@@ -50,17 +50,16 @@ def _load():
 
 def frame_records(spec: F.StreamSpec, frames: Sequence[int]) -> torch.Tensor:
     sk = F._stream_key(spec)
-    recs = torch.zeros((len(frames), FRAME_INTS), dtype=torch.int64)
-    for i, f in enumerate(frames):
+    rows = []
+    for f in frames:
         hf = F.fmix32(sk ^ F.fmix32((f + F._P_FRAME) & F.M32))
         row = [f, hf, F.drift_scale_q16(spec, f), 0]
-        objs = []
         if f >= spec.n_train:
             for o, (px, py) in zip(spec.objects, F.object_positions(spec, f)):
-                objs += [0 if o.kind == "rect" else 1, px, py, o.a, o.b, *o.colour]
+                row += [0 if o.kind == "rect" else 1, px, py, o.a, o.b, *o.colour]
             row[3] = len(spec.objects)
-        row += objs
-        recs[i, : len(row)] = torch.tensor(row, dtype=torch.int64)
+        rows.append(row + [0] * (FRAME_INTS - len(row)))
+    recs = torch.tensor(rows, dtype=torch.int64).reshape(len(rows), FRAME_INTS)
     # the frame hash is an unsigned 32-bit value: keep its bits in int32
     recs = torch.where(recs >= 2 ** 31, recs - 2 ** 32, recs)
     return recs.to(torch.int32)

@@ -339,6 +339,16 @@ def cfg3(seed: int = 3, n_streams: int = 64, n_test: int = 200) -> Workload:
     return Workload("batched-64-streams-mixed", st, d, t)
 
 
+def cfg4(seed: int = 4, n_streams: int = 256):
+    """The served mix: the batched resolution / depth / T / threshold mix plus a
+    Poisson frame rate per stream drawn uniformly from 5-30 fps.  Frames are
+    indexed from 0 without end; how many arrive depends on the duration."""
+    specs, depths, thrs = mixed_streams(n_streams, seed, n_test=0)
+    rng = random.Random(f"rates/{seed}")
+    rates = [rng.uniform(5.0, 30.0) for _ in range(n_streams)]
+    return specs, depths, thrs, rates
+
+
 def scaled(spec: StreamSpec, **kw) -> StreamSpec:
     """Same stream with some fields replaced (objects recomputed)."""
     kw.setdefault("objects", [])
