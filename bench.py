@@ -287,7 +287,7 @@ def run_served(a):
     n_frames = [len(x) for x in arrivals]
     # watched stream: the first smallest one, its masks kept for the oracle sample
     small = min(range(len(specs)), key=lambda i: (specs[i].width * specs[i].height, i))
-    wmax = n_frames[small] - specs[small].n_train
+    wmax = max(n_frames[small] - specs[small].n_train, 0)
     print(f"# served: {len(specs)} streams, {sum(n_frames)} frames over {a.serve_seconds} s; "
           f"building the frame source", file=sys.stderr, flush=True)
     ctx = IngestContext(specs, n_frames, slots=8)
@@ -295,6 +295,7 @@ def run_served(a):
     stride = max(n_frames)
 
     def serve(arr, speed, watch):
+        watch = watch and wmax > 0
         sums = np.zeros((len(specs), stride), dtype=np.uint64)
         masks = ([np.zeros((wmax, specs[small].height, (specs[small].width + 63) // 64), dtype=np.uint64)]
                  if watch else [])
@@ -375,7 +376,7 @@ def run_served(a):
         sp = specs[small]
         got, dt = oracle_served_replay(sp, depths[small], sp.n_train, *thrs[small], n_frames[small],
                                        period, window, budget_s=15.0)
-        ok = all(np.array_equal(wmasks[0][i], got[i]) for i in range(len(got)))
+        ok = bool(wmasks) and all(np.array_equal(wmasks[0][i], got[i]) for i in range(len(got)))
         px = (sp.n_train + len(got)) * sp.width * sp.height
         out["cpu_baseline"] = {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
                                "sample": f"stream {small} ({sp.width}x{sp.height}, d={depths[small]}): "

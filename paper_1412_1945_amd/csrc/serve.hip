@@ -35,17 +35,20 @@ struct ServeFrameDev {
     StripArgs a;              // geometry (one region)
     const uint8_t *rgb;
     uint32_t *occ;            // ring slot of this frame
-    uint32_t *leaf;           // the stream's merged leaf set (classify)
-    uint64_t *mask;           // test frames
-    int32_t depth, groups, spans, span, words;
-    int64_t item0;
+    uint32_t *leaf;           // the stream's merged leaf set (test frames)
+    uint64_t *mask;           // test frames; NULL for training frames
+    int32_t depth, groups, words, pad_;
+    int64_t g0;               // first group of the frame in the batch's group space
 };
 
+// A batch is one space of 16-pixel groups: its frames' groups end to end.
+// Workgroup w takes groups [w*chunk, (w+1)*chunk), whatever frames they fall
+// in, so every workgroup has the same number of pixels to read.
 struct ServeArgs {
     const ServeFrameDev *frames;
     int32_t n_frames;
-    int64_t n_items;
-    int32_t stage_mask;
+    int64_t n_groups;
+    int64_t chunk;            // multiple of 4: mask words never straddle workgroups
 };
 
 struct MergeJobDev {
@@ -57,12 +60,14 @@ struct MergeJobDev {
 };
 
 constexpr int kServeTableWords = 8192;
+constexpr int kServeBlock = 512;
 
-__device__ __forceinline__ int frame_of(const ServeArgs &b, int64_t it) {
+// The frame holding group g: the last frame whose first group is <= g.
+__device__ __forceinline__ int frame_of(const ServeArgs &b, int64_t g) {
     int lo = 0, hi = b.n_frames - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (b.frames[mid].item0 <= it)
+        if (b.frames[mid].g0 <= g)
             lo = mid;
         else
             hi = mid - 1;
@@ -70,60 +75,62 @@ __device__ __forceinline__ int frame_of(const ServeArgs &b, int64_t it) {
     return lo;
 }
 
+// Groups [gb, ge) of one frame: its occupancy is built in LDS and ORed into the
+// frame's ring slot; test frames also get their mask bits from the leaf table.
 template <int D, int LAY, int MODE>
-__device__ __attribute__((noinline)) void serve_item(const ServeArgs &b, const ServeFrameDev &fd, int64_t local,
-                                                     uint32_t *leaf_tab, uint32_t *occ_tab, uint16_t *st_mask,
-                                                     bool new_frame, bool new_leaf) {
+__device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, int gb, int ge, uint32_t *leaf_tab,
+                                                     uint32_t *occ_tab, bool load_leaf) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr int LW = lds_words(D, LAY);
     const int tid = threadIdx.x;
     const StripArgs a = fd.a;
-    if (MASK && new_leaf) {
-        __syncthreads();
-        leaf_to_lds<D, LAY>(fd.leaf, leaf_tab, 1, tid, 256);
-    }
+    if (MASK && load_leaf) leaf_to_lds<D, LAY>(fd.leaf, leaf_tab, 1, tid, kServeBlock);
     __syncthreads();
-    for (int i = tid; i < LW; i += 256) occ_tab[i] = 0;
+    for (int i = tid; i < LW; i += kServeBlock) occ_tab[i] = 0;
     __syncthreads();
-    const int t = (int)local;
-    const int gb = t * fd.span;
-    const int ge = min(gb + fd.span, fd.groups);
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(fd.rgb, (uint32_t)a.frame_pitch);
     __amdgpu_buffer_rsrc_t ms = make_rsrc(nullptr, 0);
     if (MASK) ms = make_rsrc(fd.mask, (uint32_t)a.height * (uint32_t)a.mask_row_words * 8u);
-    uint16_t *stage = (MASK && b.stage_mask) ? st_mask : nullptr;
-    span_loop<D, MODE, LAY, false, 256>(a, rs, ms, gb, ge, leaf_tab, occ_tab, nullptr, stage);
+    span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, leaf_tab, occ_tab, nullptr, nullptr);
     __syncthreads();
-    occ_from_lds<D, LAY>(occ_tab, fd.occ, 1, tid, 256);
-    (void)new_frame;
+    occ_from_lds<D, LAY>(occ_tab, fd.occ, 1, tid, kServeBlock);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void serve_kernel(ServeArgs b) {
-    constexpr bool MASK = (MODE & MODE_MASK) != 0;
-    __shared__ uint32_t leaf_tab[MASK ? kServeTableWords : 1];
+__device__ __forceinline__ void serve_dispatch(const ServeFrameDev &fd, int gb, int ge, uint32_t *leaf_tab,
+                                               uint32_t *occ_tab, bool load_leaf) {
+    switch (fd.depth) {
+        case 1: serve_part<1, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
+        case 2: serve_part<2, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
+        case 3: serve_part<3, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
+        case 4: serve_part<4, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
+        case 5: serve_part<5, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
+        default: serve_part<6, LAY_COMPACT, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
+    }
+}
+
+// Training frames (occupancy) and test frames (mask and occupancy) of a batch
+// in one launch.
+__global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))) void serve_kernel(ServeArgs b) {
+    __shared__ uint32_t leaf_tab[kServeTableWords];
     __shared__ uint32_t occ_tab[kServeTableWords];
-    __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
-    const int64_t i0 = b.n_items * blockIdx.x / gridDim.x;
-    const int64_t i1 = b.n_items * (blockIdx.x + 1) / gridDim.x;
-    int cur = -1;
+    int64_t g = (int64_t)blockIdx.x * b.chunk;
+    const int64_t gend = min(g + b.chunk, b.n_groups);
+    if (g >= gend) return;
+    int fi = frame_of(b, g);
     const uint32_t *cur_leaf = nullptr;
-    for (int64_t it = i0; it < i1; ++it) {
-        const int fi = frame_of(b, it);
+    while (g < gend && fi < b.n_frames) {
         const ServeFrameDev &fd = b.frames[fi];
-        const int64_t local = it - fd.item0;
-        const bool fresh = fi != cur;
-        const bool new_leaf = fd.leaf != cur_leaf;
-        switch (fd.depth) {
-            case 1: serve_item<1, LAY_WIDE, MODE>(b, fd, local, leaf_tab, occ_tab, st_mask, fresh, new_leaf); break;
-            case 2: serve_item<2, LAY_WIDE, MODE>(b, fd, local, leaf_tab, occ_tab, st_mask, fresh, new_leaf); break;
-            case 3: serve_item<3, LAY_WIDE, MODE>(b, fd, local, leaf_tab, occ_tab, st_mask, fresh, new_leaf); break;
-            case 4: serve_item<4, LAY_WIDE, MODE>(b, fd, local, leaf_tab, occ_tab, st_mask, fresh, new_leaf); break;
-            case 5: serve_item<5, LAY_WIDE, MODE>(b, fd, local, leaf_tab, occ_tab, st_mask, fresh, new_leaf); break;
-            default: serve_item<6, LAY_COMPACT, MODE>(b, fd, local, leaf_tab, occ_tab, st_mask, fresh, new_leaf); break;
+        const int lb = (int)(g - fd.g0);
+        const int le = (int)min<int64_t>(gend - fd.g0, (int64_t)fd.groups);
+        if (fd.mask) {
+            serve_dispatch<MODE_MASK | MODE_OCC>(fd, lb, le, leaf_tab, occ_tab, fd.leaf != cur_leaf);
+            cur_leaf = fd.leaf;
+        } else {
+            serve_dispatch<MODE_OCC>(fd, lb, le, leaf_tab, occ_tab, false);
         }
-        cur = fi;
-        cur_leaf = fd.leaf;
+        g = fd.g0 + le;
+        ++fi;
     }
 }
 
@@ -248,8 +255,7 @@ double union_length(std::vector<std::pair<double, double>> iv) {
     return total;
 }
 
-void fill_frame(ServeFrameDev &fd, const StreamState &ss, const uint8_t *rgb, uint32_t *occ, uint64_t *mask,
-                int span_target) {
+void fill_frame(ServeFrameDev &fd, const StreamState &ss, const uint8_t *rgb, uint32_t *occ, uint64_t *mask) {
     fd.a = ss.a;
     fd.rgb = rgb;
     fd.occ = occ;
@@ -257,10 +263,8 @@ void fill_frame(ServeFrameDev &fd, const StreamState &ss, const uint8_t *rgb, ui
     fd.mask = mask;
     fd.depth = ss.cfg.depth;
     fd.groups = ss.groups;
-    int64_t s = (std::min<int64_t>(span_target, ss.groups) + 3) & ~int64_t(3);
-    fd.spans = (int)((ss.groups + s - 1) / s);
-    fd.span = (int)((((ss.groups + fd.spans - 1) / fd.spans) + 3) & ~3);
     fd.words = ss.words;
+    fd.pad_ = 0;
 }
 
 void merge_job(MergeJobDev &j, const StreamState &ss, int first, int n, uint32_t num, uint32_t den) {
@@ -495,29 +499,17 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             rr = (rr + 1) % ns;
             const int nt = (int)train_list.size(), nc = (int)test_list.size();
             if (nt + nc > 0) {
-                // descriptors: training frames first, then test frames
-                int64_t it0 = 0;
-                for (int i = 0; i < nt; ++i) {
-                    const PendingFrame &pf = train_list[i];
+                // descriptors: training frames first, then test frames, their
+                // groups numbered end to end
+                int64_t n_groups = 0;
+                for (int i = 0; i < nt + nc; ++i) {
+                    const PendingFrame &pf = i < nt ? train_list[i] : test_list[i - nt];
                     StreamState &ss = S[pf.stream];
                     ServeFrameDev &fd = sl.h_frames[i];
-                    fill_frame(fd, ss, pf.rgb, ss.ring + (int64_t)(pf.frame % ss.ring_len) * ss.words, nullptr, 1 << 20);
-                    fd.item0 = it0;
-                    it0 += fd.spans;
+                    fill_frame(fd, ss, pf.rgb, ss.ring + (int64_t)(pf.frame % ss.ring_len) * ss.words, pf.mask);
+                    fd.g0 = n_groups;
+                    n_groups += ss.groups;
                 }
-                const int64_t train_items = it0;
-                it0 = 0;
-                for (int i = 0; i < nc; ++i) {
-                    const PendingFrame &pf = test_list[i];
-                    StreamState &ss = S[pf.stream];
-                    ServeFrameDev &fd = sl.h_frames[nt + i];
-                    // one item per frame up to 1M pixels: the fused pass flushes its
-                    // occupancy table once per item
-                    fill_frame(fd, ss, pf.rgb, ss.ring + (int64_t)(pf.frame % ss.ring_len) * ss.words, pf.mask, 1 << 16);
-                    fd.item0 = it0;
-                    it0 += fd.spans;
-                }
-                const int64_t test_items = it0;
                 sl.frames.clear();
                 for (auto &pf : train_list) sl.frames.push_back(pf);
                 for (auto &pf : test_list) sl.frames.push_back(pf);
@@ -543,15 +535,16 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 if (ok) {
                     hipLaunchKernelGGL(serve_zero_kernel, dim3(8, nt + nc), dim3(256), 0, st,
                                        (const ServeFrameDev *)sl.d_frames);
-                    if (nt) {
-                        ServeArgs b{sl.d_frames, nt, train_items, 0};
-                        const int grid = (int)std::min<int64_t>(train_items, cus * 2);
-                        hipLaunchKernelGGL((serve_kernel<MODE_OCC>), dim3(grid), dim3(256), 0, st, b);
-                    }
-                    if (nc) {
-                        ServeArgs b{sl.d_frames + nt, nc, test_items, 0};
-                        const int grid = (int)std::min<int64_t>(test_items, cus * 2);
-                        hipLaunchKernelGGL((serve_kernel<MODE_MASK | MODE_OCC>), dim3(grid), dim3(256), 0, st, b);
+                    {
+                        // equal runs of groups, at least kMinChunk per workgroup
+                        // so that a small batch does not pay for idle workgroups
+                        const int64_t kMinChunk = 2048;
+                        int64_t grid = std::min<int64_t>((n_groups + kMinChunk - 1) / kMinChunk, (int64_t)cus * 2);
+                        grid = std::max<int64_t>(grid, 1);
+                        const int64_t chunk = (((n_groups + grid - 1) / grid) + 3) & ~int64_t(3);
+                        grid = (n_groups + chunk - 1) / chunk;
+                        ServeArgs b{sl.d_frames, nt + nc, n_groups, chunk};
+                        hipLaunchKernelGGL(serve_kernel, dim3((unsigned)grid), dim3(kServeBlock), 0, st, b);
                     }
                     if (n_jobs) {
                         int maxw = 1;
