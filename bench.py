@@ -40,8 +40,8 @@ def parse():
                    help="seconds of arrivals offered all at once to measure the served capacity")
     p.add_argument("--serve-budget-gib", type=float, default=32.0)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-sample-test", type=int, default=900,
-                   help="test frames in the oracle's timed sample")
+    p.add_argument("--cpu-seconds", type=float, default=15.0,
+                   help="time budget of the oracle's timed sample (all training frames, then test frames)")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "classify_traffic.json"),
                    help="HBM traffic of the classify kernel measured with rocprofv3 counters")
     p.add_argument("--probe", action="store_true",
@@ -52,7 +52,7 @@ def parse():
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for name in ("kernels.hip", "device.h", "internal.h", "api.hip"):
+    for name in ("kernels.hip", "device.h", "internal.h", "strip_core.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_1412_1945_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -63,14 +63,16 @@ def run_probes(obg, torch, src, nbytes, reps=5):
     dst = torch.empty(max(nbytes // 24, 1 << 30) + 4096, dtype=torch.uint8, device=src.device)
     sink = torch.empty(512 * 512, dtype=torch.int32, device=src.device)
     out = {}
+    big = src if src.numel() >= (1 << 30) else torch.empty(1 << 30, dtype=torch.uint8, device=src.device).fill_(7)
     for name, kind, n in [("read", obg.PROBE_READ, nbytes), ("read_write", obg.PROBE_READ_WRITE, nbytes),
                           ("copy_1gib", obg.PROBE_COPY, 1 << 30)]:
+        s_in = big if kind == obg.PROBE_COPY else src
         times = []
         for r in range(reps + 1):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
-            obg.obg_probe(kind, src, dst, n, sink, 512)
+            obg.obg_probe(kind, s_in, dst, n, sink, 512)
             b.record()
             torch.cuda.synchronize()
             if r:
@@ -90,22 +92,32 @@ def workload(name, n_test):
     return S.cfg0()
 
 
-def cpu_baseline(host_train, host_test, spec, depth, num, den, region):
-    """The oracle as it is, single-threaded, on every training frame and a
-    sample of test frames of the same workload."""
+def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, budget_s):
+    """The oracle as it is, single-threaded: trees of every training frame, the
+    merge, then test frames (fetched one at a time) until `budget_s` seconds
+    have passed or `n_test` frames are classified."""
     from oracle import octree
     t0 = time.perf_counter()
     f = octree.Forest(spec.width, spec.height, depth, region[0], region[1])
     idx = f.add_frames(host_train)
     model = f.merge(idx, num, den)
-    for fr in host_test:
+    t_train = time.perf_counter() - t0
+    done = 0
+    t_cls = 0.0
+    while done < n_test and t_train + t_cls < budget_s:
+        fr = test_frame(done)
+        t1 = time.perf_counter()
         model.classify(fr)
-    dt = time.perf_counter() - t0
-    px = (len(host_train) + len(host_test)) * spec.pixels
+        t_cls += time.perf_counter() - t1
+        done += 1
+    dt = t_train + t_cls
+    px = (len(host_train) + done) * spec.pixels
     return {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(host_train)} training frames (trees + merge) and {len(host_test)} test "
-                      f"frames (classify) of the same stream, {spec.width}x{spec.height}, "
-                      f"{dt:.1f} s single-threaded"}
+            "sample": f"{len(host_train)} training frames (trees + merge, {t_train:.1f} s) and {done} test "
+                      f"frames (classify, {t_cls:.1f} s) of the same stream, {spec.width}x{spec.height}, "
+                      f"single-threaded",
+            "train_gpixel_s": round(len(host_train) * spec.pixels / t_train / 1e9, 5),
+            "classify_gpixel_s": round(done * spec.pixels / t_cls / 1e9, 5) if done else None}
 
 
 def run_batched(a):
@@ -462,6 +474,22 @@ def main():
     cls_ms = sorted(e[0].elapsed_time(e[1]) for e in evs)
     cls_avg = sum(cls_ms) / len(cls_ms)
 
+    # the fused pass of the serving path: mask and the frame's occupancy in one read
+    occ_t = obg.empty_occ(g, N)
+    mask_f = obg.empty_mask(g, N)
+    fused = []
+    for r in range(min(a.steps, 10) + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        obg.obg_classify(g, test, N, leaf, mask_f, occ_t)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            fused.append(e0.elapsed_time(e1))
+    fused_ms = sum(fused) / len(fused)
+    fused_same = bool(torch.equal(mask_f, mask))
+    occ_bytes = N * g.n_regions * g.words * 4
+
     px_step = (T + N) * spec.pixels
     value = px_step / (ms_step * 1e-3) / 1e9
     cls_bytes = N * (3 * spec.pixels + spec.height * g.mask_row_words * 8)
@@ -496,6 +524,10 @@ def main():
         "classify": {"ms_avg": round(cls_avg, 4), "ms_p50": round(cls_ms[len(cls_ms) // 2], 4),
                      "gpixel_s": round(N * spec.pixels / (cls_avg * 1e-3) / 1e9, 3)},
         "train_merge_ms": round(ms_step - cls_avg, 4),
+        "classify_occ": {"ms_avg": round(fused_ms, 4),
+                         "gpixel_s": round(N * spec.pixels / (fused_ms * 1e-3) / 1e9, 3),
+                         "tb_s": round((cls_bytes + occ_bytes) / (fused_ms * 1e-3) / 1e12, 3),
+                         "mask_equal_unfused": fused_same},
         "probe": probes,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -505,10 +537,9 @@ def main():
     }
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
-        ns = min(a.cpu_sample_test, N)
         host_train = list(train.cpu().numpy())
-        host_test = list(test[:ns].cpu().numpy())
-        out["cpu_baseline"] = cpu_baseline(host_train, host_test, spec, depth, num, den, (rw, rh))
+        out["cpu_baseline"] = cpu_baseline(host_train, lambda i: test[i].cpu().numpy(), N, spec, depth,
+                                           num, den, (rw, rh), a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -212,6 +212,15 @@ void obg_batch_destroy(obg_batch *batch);
  * to host buffers (watch_masks[w], [watch_max_frames][height][ceil(width/64)]).
  * Streams: plain geometry, depth 1..6; pixels are packed RGB8 with row pitch
  * 3*width rounded up to 16 bytes.
+ * Admission: a frame takes one arena block (its pixels, and for a test frame
+ * its mask).  When a frame does not fit, its stream goes first and no other
+ * frame is admitted until it does, so no stream starves; a frame that cannot
+ * fit even with nothing in flight ends the run with OBG_ENOMEM.  The library
+ * allocates the arena, its slots' staging buffers and streams at the start of
+ * the run and frees them before returning.
+ * Errors: OBG_EINVAL (bad configuration), OBG_ENOMEM (budget or allocation),
+ * OBG_EHIP (a launch or a batch failed, or the scheduler stopped making
+ * progress).  Statistics are filled in either way.
  */
 typedef struct obg_ingest_item {
     int32_t stream;

@@ -93,7 +93,25 @@ int cu_count() {
     return cache[dev];
 }
 
-const size_t kStripLdsMax = 64 * 1024;
+// LDS one workgroup of the strip kernel may hold for its tables: the device's
+// per-workgroup limit (160 KiB on gfx950) less room for the kernel's static
+// arrays (mask staging).
+size_t strip_lds_max() {
+    static std::mutex mu;
+    static size_t cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 64 * 1024;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!cache[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || n <= 0)
+            n = 64 * 1024;
+        size_t lim = (size_t)n;
+        if (lim > 160 * 1024) lim = 160 * 1024;
+        cache[dev] = lim > 64 * 1024 ? lim - 4 * 1024 : lim;
+    }
+    return cache[dev];
+}
 
 // Launch-shape knobs of the pixel kernels (0 = built-in default).
 int g_tune[OBG_TUNE_COUNT] = {0};
@@ -110,12 +128,15 @@ bool strip_ok(const Geo &g, int mode, int *lay) {
     if (g.depth > 6) return false;
     if (g.region_w && (g.region_w % 16) != 0) return false;
     const size_t wide = strip_lds_bytes(g.depth, mode, g.reg_cols, LAY_WIDE);
-    if (wide && wide <= kStripLdsMax && tune(OBG_TUNE_LAYOUT, 1) == 1) {
+    // the wide order when its tables fit in 64 KiB (several workgroups per
+    // CU); compact tables of many regions may fill the workgroup's whole LDS
+    if (wide && wide <= 64 * 1024 && tune(OBG_TUNE_LAYOUT, 1) == 1) {
         *lay = LAY_WIDE;
         return true;
     }
     *lay = LAY_COMPACT;
-    return strip_lds_bytes(g.depth, mode, g.reg_cols, LAY_COMPACT) <= kStripLdsMax;
+    const size_t cap = g.reg_cols > 1 ? strip_lds_max() : 64 * 1024;
+    return strip_lds_bytes(g.depth, mode, g.reg_cols, LAY_COMPACT) <= cap;
 }
 
 int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, const uint32_t *leaf,
@@ -172,8 +193,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     // classify: large tables leave room for few workgroups per CU; 512-thread
     // groups keep the CU at its 32 waves with 4 of them
     const size_t lds_need = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
-    const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024)
-                               : (mode == MODE_MASK ? tune(OBG_TUNE_CLASSIFY_BLOCK, 512) : 256);
+    const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024) : tune(OBG_TUNE_CLASSIFY_BLOCK, 512);
     (void)lds_need;
     if (occ_only && block != 256 && block != 1024) return fail(OBG_EINVAL, "train block size must be 256 or 1024");
     if (!occ_only && block != 256 && block != 512) return fail(OBG_EINVAL, "classify block size must be 256 or 512");

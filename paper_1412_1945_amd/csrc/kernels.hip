@@ -24,7 +24,9 @@
 namespace obg {
 
 template <int D, int MODE, int BLOCK, int PAD, bool REGION>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu((MODE == MODE_MASK && D == 5) ? 8 : 1))) void strip_kernel(StripArgs a) {
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
+    (MODE == MODE_MASK && D == 5) ? 8 : ((MODE == (MODE_MASK | MODE_OCC) && BLOCK == 512) ? 4 : 1)))) void
+strip_kernel(StripArgs a) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
@@ -159,27 +161,45 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
 // ---------------------------------------------------------------------------
 // Launchers
 
+// Dynamic LDS above 64 KiB (region tables on gfx950) has to be allowed per kernel.
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds);
+}
+
+#define OBG_LAUNCH(K, BLK)                                                  \
+    do {                                                                    \
+        const hipError_t e_ = allow_lds(K, lds);                            \
+        if (e_ != hipSuccess) return e_;                                    \
+        hipLaunchKernelGGL(K, dim3(grid), dim3(BLK), lds, st, a);           \
+    } while (0)
+
 template <int D, int LAY, bool REGION>
 static hipError_t launch_variant(int mode, int block, const StripArgs &a, int grid, size_t lds,
                                  hipStream_t st) {
     switch (mode) {
         case MODE_MASK:
             if (block == 512)
-                hipLaunchKernelGGL((strip_kernel<D, MODE_MASK, 512, LAY, REGION>), dim3(grid), dim3(512), lds, st, a);
+                OBG_LAUNCH((strip_kernel<D, MODE_MASK, 512, LAY, REGION>), 512);
             else
-                hipLaunchKernelGGL((strip_kernel<D, MODE_MASK, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+                OBG_LAUNCH((strip_kernel<D, MODE_MASK, 256, LAY, REGION>), 256);
             break;
         case MODE_OCC:
             if (block == 1024)
-                hipLaunchKernelGGL((strip_kernel<D, MODE_OCC, 1024, LAY, REGION>), dim3(grid), dim3(1024), lds, st, a);
+                OBG_LAUNCH((strip_kernel<D, MODE_OCC, 1024, LAY, REGION>), 1024);
             else
-                hipLaunchKernelGGL((strip_kernel<D, MODE_OCC, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+                OBG_LAUNCH((strip_kernel<D, MODE_OCC, 256, LAY, REGION>), 256);
             break;
         case MODE_MASK | MODE_OCC:
-            hipLaunchKernelGGL((strip_kernel<D, MODE_MASK | MODE_OCC, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+            if (block == 512)
+                OBG_LAUNCH((strip_kernel<D, MODE_MASK | MODE_OCC, 512, LAY, REGION>), 512);
+            else
+                OBG_LAUNCH((strip_kernel<D, MODE_MASK | MODE_OCC, 256, LAY, REGION>), 256);
             break;
         case MODE_OCC | MODE_COUNTS:
-            hipLaunchKernelGGL((strip_kernel<D, MODE_OCC | MODE_COUNTS, 256, LAY, REGION>), dim3(grid), dim3(256), lds, st, a);
+            OBG_LAUNCH((strip_kernel<D, MODE_OCC | MODE_COUNTS, 256, LAY, REGION>), 256);
             break;
         default:
             return hipErrorInvalidValue;

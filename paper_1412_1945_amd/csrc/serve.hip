@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/obg.h"
+#include "arena.h"
 #include "strip_core.h"
 
 namespace obg {
@@ -166,42 +167,6 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-// Budgeted device arena: one allocation, size classes with free lists.
-struct Arena {
-    uint8_t *base = nullptr;
-    uint64_t size = 0, top = 0, in_use = 0, peak = 0;
-    std::vector<std::pair<uint64_t, std::vector<uint64_t>>> free_lists;   // (class size, offsets)
-
-    static uint64_t round(uint64_t b) { return (b + 255) & ~uint64_t(255); }
-    uint8_t *get(uint64_t bytes) {
-        bytes = round(bytes);
-        for (auto &fl : free_lists)
-            if (fl.first == bytes && !fl.second.empty()) {
-                uint64_t off = fl.second.back();
-                fl.second.pop_back();
-                in_use += bytes;
-                peak = std::max(peak, in_use);
-                return base + off;
-            }
-        if (top + bytes > size) return nullptr;
-        uint64_t off = top;
-        top += bytes;
-        in_use += bytes;
-        peak = std::max(peak, in_use);
-        return base + off;
-    }
-    void put(uint8_t *p, uint64_t bytes) {
-        bytes = round(bytes);
-        in_use -= bytes;
-        for (auto &fl : free_lists)
-            if (fl.first == bytes) {
-                fl.second.push_back((uint64_t)(p - base));
-                return;
-            }
-        free_lists.push_back({bytes, {(uint64_t)(p - base)}});
-    }
-};
-
 struct StreamState {
     obg_serve_stream cfg;
     StripArgs a{};
@@ -213,15 +178,16 @@ struct StreamState {
     int inflight = 0;           // batches holding frames of this stream
     int inflight_frames = 0;    // frames of this stream in those batches
     bool merge_inflight = false;
-    bool admitted = false;
+    bool head_waited = false;   // the first queued frame has already been refused once
 };
 
 struct PendingFrame {
     int stream, frame;
     double arrival;             // wall seconds after start
-    uint8_t *rgb;
+    uint8_t *rgb;               // frame, then (test frames) its mask, in one arena block
     uint64_t *mask;
     bool test;
+    uint64_t bytes;             // size of the arena block
 };
 
 struct Slot {
@@ -283,6 +249,10 @@ void merge_job(MergeJobDev &j, const StreamState &ss, int first, int n, uint32_t
     while ((1 << j.planes) <= n) ++j.planes;
 }
 
+uint64_t frame_block(const StreamState &ss, bool test) {
+    return Arena::round(ss.frame_bytes) + (test ? Arena::round(ss.mask_bytes) : 0);
+}
+
 }  // namespace
 
 extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats) {
@@ -337,9 +307,10 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     std::stable_sort(arr.begin(), arr.end(), [](const Arr &x, const Arr &y) { return x.t < y.t; });
 
     Arena arena;
-    arena.size = cfg->budget_bytes;
-    hipError_t e = hipMalloc(&arena.base, arena.size);
+    uint8_t *arena_mem = nullptr;
+    hipError_t e = hipMalloc(&arena_mem, cfg->budget_bytes);
     if (e != hipSuccess) return sfail(OBG_ENOMEM, "arena allocation failed");
+    arena.init(arena_mem, cfg->budget_bytes);
     int rc = OBG_OK;
     const int M = cfg->max_inflight;
     std::vector<Slot> slots(M);
@@ -386,7 +357,10 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     }
     const Clock::time_point start = Clock::now();
     auto wall_now = [&]() { return std::chrono::duration<double>(Clock::now() - start).count(); };
-    int rr = 0;   // round-robin start among streams
+    int rr = 0;         // round-robin start among streams
+    double idle_since = -1;
+    int waiting = -1;   // stream whose next frame did not fit: it goes first, and
+                        // nothing else is admitted until it fits
     while (rc == OBG_OK) {
         // 1. arrivals up to now (simulated time = wall time * speed)
         const double vt = wall_now() * cfg->speed;
@@ -424,8 +398,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                     train_pixels += (int64_t)ss.cfg.width * ss.cfg.height;
                 }
                 pixels += (int64_t)ss.cfg.width * ss.cfg.height;
-                arena.put(pf.rgb, ss.frame_bytes);
-                if (pf.mask) arena.put((uint8_t *)pf.mask, ss.mask_bytes);
+                arena.put(pf.rgb, pf.bytes);
                 ++served;
             }
             for (auto &pf : sl.frames) S[pf.stream].inflight_frames--;
@@ -455,8 +428,11 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             std::vector<PendingFrame> train_list, test_list;
             int n_jobs = 0;
             bool blocked = false;
+            // each stream is visited at most once per batch: a stream's frames
+            // after one that ends with a merge must not join the same batch
+            const int first_stream = waiting >= 0 ? waiting : rr;
             for (int k = 0; k < ns && (int)(train_list.size() + test_list.size()) < maxf && !blocked; ++k) {
-                const int s = (rr + k) % ns;
+                const int s = (first_stream + k) % ns;
                 StreamState &ss = S[s];
                 const int T = ss.cfg.n_train;
                 bool merged_here = false;
@@ -471,13 +447,18 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                     // ring slots of frames in flight must stay distinct
                     if (ss.inflight_frames + 1 > ss.ring_len / 2) break;
                     // frames that follow a merge in this batch wait for the next batch
-                    PendingFrame pf{s, f, 0.0, nullptr, nullptr, test};
-                    pf.rgb = arena.get(ss.frame_bytes);
-                    if (pf.rgb && test) {
-                        pf.mask = (uint64_t *)arena.get(ss.mask_bytes);
-                        if (!pf.mask) { arena.put(pf.rgb, ss.frame_bytes); pf.rgb = nullptr; }
+                    PendingFrame pf{s, f, 0.0, nullptr, nullptr, test, frame_block(ss, test)};
+                    pf.rgb = arena.get(pf.bytes);
+                    if (!pf.rgb) {
+                        if (!ss.head_waited) ++admission_waits;
+                        ss.head_waited = true;
+                        waiting = s;
+                        blocked = true;
+                        break;
                     }
-                    if (!pf.rgb) { ++admission_waits; blocked = true; break; }
+                    ss.head_waited = false;
+                    if (waiting == s) waiting = -1;
+                    if (test) pf.mask = (uint64_t *)(pf.rgb + Arena::round(ss.frame_bytes));
                     pf.arrival = cfg->arrivals[s][f] / cfg->speed;
                     ss.queued.pop_front();
                     ss.inflight_frames++;
@@ -582,19 +563,31 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 launched = true;
             }
         }
+        if (launched || progressed) idle_since = -1;
         if (!launched && !progressed) {
             bool any_busy = false;
             for (auto &sl : slots) any_busy = any_busy || sl.busy;
+            // nothing in flight holds arena memory: a frame that does not
+            // fit now never will
+            if (!any_busy && waiting >= 0 && !S[waiting].queued.empty()) {
+                const StreamState &ws = S[waiting];
+                if (frame_block(ws, ws.queued.front() >= ws.cfg.n_train) > arena.largest()) {
+                    rc = sfail(OBG_ENOMEM, "budget too small for one frame");
+                    break;
+                }
+            }
+            // with nothing in flight every queued frame is admissible; frames
+            // that stay queued would mean a scheduling fault: stop, do not spin
             bool any_queued = false;
             for (auto &ss : S) any_queued = any_queued || !ss.queued.empty();
-            // nothing in flight, frames waiting, and none could be admitted:
-            // the budget cannot hold even one frame
-            if (!any_busy && any_queued && admission_waits > 0 && next_arr == arr.size()) {
-                bool none_fits = true;
-                for (auto &ss : S)
-                    if (!ss.queued.empty() && ss.frame_bytes + ss.mask_bytes + 512 <= arena.size - arena.in_use)
-                        none_fits = false;
-                if (none_fits) { rc = sfail(OBG_ENOMEM, "budget too small for one frame"); break; }
+            if (!any_busy && any_queued) {
+                if (idle_since < 0) idle_since = wall_now();
+                if (wall_now() - idle_since > 2.0) {
+                    rc = sfail(OBG_EHIP, "serving loop stalled with frames queued and nothing in flight");
+                    break;
+                }
+            } else {
+                idle_since = -1;
             }
             std::this_thread::sleep_for(std::chrono::microseconds(20));
         }

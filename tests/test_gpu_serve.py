@@ -71,22 +71,29 @@ def _oracle_masks(O, spec, stream, n_frames):
     return out
 
 
+def _check_oracle(O, specs, streams, arrivals, masks):
+    bad = []
+    for w, m in enumerate(masks):
+        T = streams[w]["n_train"]
+        want = _oracle_masks(O, specs[w], streams[w], len(arrivals[w]))
+        got = m[: len(arrivals[w]) - T]
+        assert len(want) == len(got)
+        wrong = [t for t in range(len(want)) if not np.array_equal(got[t], want[t])]
+        if wrong:
+            bad.append(f"stream {w}: {len(wrong)} of {len(want)} test frames differ, first {wrong[:12]}")
+    assert not bad, "; ".join(bad)
+
+
 def test_serve_matches_oracle_and_alone(env):
     obg, O = env
     specs, streams, arrivals = _setup()
     every = list(range(len(specs)))
     print(f"[case] serve mix of {len(specs)} streams, {sum(len(a) for a in arrivals)} frames", flush=True)
-    stats, sums, masks = _serve(obg, specs, streams, arrivals, every, watch=(1, 3))
+    stats, sums, masks = _serve(obg, specs, streams, arrivals, every, watch=every)
     assert stats["frames_served"] == stats["frames_arrived"] == sum(len(a) for a in arrivals)
     assert stats["merges"] >= len(specs) * 5
     assert stats["batches"] > 1
-    for w, m in zip((1, 3), masks):
-        T = streams[w]["n_train"]
-        want = _oracle_masks(O, specs[w], streams[w], len(arrivals[w]))
-        got = m[: len(arrivals[w]) - T]
-        assert len(want) == len(got)
-        for t in range(len(want)):
-            assert np.array_equal(got[t], want[t]), f"stream {w} test frame {t}"
+    _check_oracle(O, specs, streams, arrivals, masks)
     for w in (0, 2, 4):
         print(f"[case] serve stream {w} alone", flush=True)
         _, alone, _ = _serve(obg, specs, streams, arrivals, [w])
@@ -97,19 +104,40 @@ def test_serve_matches_oracle_and_alone(env):
 
 
 def test_serve_tight_budget_same_results(env):
+    """Frames wait for memory; each stream still gets every frame, in order,
+    with the results of an unconstrained run."""
     obg, O = env
     specs, streams, arrivals = _setup()
     every = list(range(len(specs)))
     _, ref, _ = _serve(obg, specs, streams, arrivals, every)
-    # rings and leaf sets of all streams, plus room for about three frames
+    # rings and leaf sets of all streams, plus room for one frame of the
+    # largest stream; every arrival is offered at once
     state = 0
     for s in streams:
         words = max(1, (1 << (3 * s["depth"])) // 32)
         ring = max(s["n_train"], WINDOW)
         state += ((ring * words * 4 + 255) // 256) * 256 + ((words * 4 + 255) // 256) * 256
     frame = ((64 * 384 + 255) // 256) * 256 + 1024      # largest frame and its mask
-    print(f"[case] serve with budget {state + 3 * frame}", flush=True)
-    stats, sums, _ = _serve(obg, specs, streams, arrivals, every, budget=state + 3 * frame, speed=4.0)
+    print(f"[case] serve with budget {state + frame}", flush=True)
+    stats, sums, masks = _serve(obg, specs, streams, arrivals, every, budget=state + frame, speed=1000.0,
+                                watch=every)
     assert stats["admission_waits"] > 0
     assert stats["frames_served"] == stats["frames_arrived"]
+    _check_oracle(O, specs, streams, arrivals, masks)
     assert np.array_equal(sums, ref)
+
+
+def test_serve_budget_below_one_frame_is_an_error(env):
+    """A budget that holds the streams' state but not one frame ends the run
+    with an error instead of waiting forever."""
+    obg, O = env
+    specs, streams, arrivals = _setup()
+    state = 0
+    for s in streams:
+        words = max(1, (1 << (3 * s["depth"])) // 32)
+        ring = max(s["n_train"], WINDOW)
+        state += ((ring * words * 4 + 255) // 256) * 256 + ((words * 4 + 255) // 256) * 256
+    print(f"[case] serve with budget {state + 2048} (no frame fits)", flush=True)
+    with pytest.raises(obg.ObgError) as e:
+        _serve(obg, specs, streams, arrivals, list(range(len(specs))), budget=state + 2048, speed=1000.0)
+    assert e.value.code == -4

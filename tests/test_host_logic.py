@@ -12,3 +12,11 @@ def test_fastdiv_and_key_permutation(tmp_path):
                    check=True, capture_output=True)
     r = subprocess.run([exe], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
+
+
+def test_serving_arena(tmp_path):
+    exe = str(tmp_path / "arena_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", os.path.join(HERE, "host", "arena_check.cpp"), "-o", exe],
+                   check=True, capture_output=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
