@@ -203,7 +203,7 @@ void obg_batch_destroy(obg_batch *batch);
  *   n_train is test frame t = f - n_train; after every `remerge_period`-th
  *   test frame the model becomes the merge of the last `remerge_window`
  *   frames' trees (same threshold), used from the next frame on (a reading
- *   of the paper's "octree updation", which gives no procedure).
+ *   of the tree update that the paper names but does not define).
  *   Per stream, results do not depend on what else is in the mix.
  * Latency of a test frame = time its mask is complete in HBM minus its
  * arrival (wall clock).  Outputs for checking: per-frame mask checksums

@@ -5,18 +5,20 @@
 // forms a batch of frames from many streams, and enqueues it on one of
 // several HIP streams, so that batches overlap on the device:
 //   ingest    the frames' pixels are written into their buffers (callback);
-//   train     training frames: occupancy into the stream's ring slot
-//             (Algorithm 1 with the pruning of Section 2);
-//   classify  test frames: mask and occupancy in one pass (Algorithm 3, and
-//             the frame's tree for later re-merges);
+//   frames    one launch over all frames of the batch: training frames
+//             write their occupancy into the stream's ring slot (Algorithm 1
+//             with the pruning of Section 2); test frames write their mask
+//             and their occupancy in the same pass (Algorithm 3, and the
+//             frame's tree for later re-merges);
 //   merge     the initial model after the training frames, and every
 //             `period` test frames a re-merge over the last `window` ring
-//             slots (Algorithm 2; the paper's "octree updation" has no
-//             procedure of its own, this is the reading used here).
+//             slots (Algorithm 2; Section 4 names an update of the tree but
+//             gives no procedure, this is the reading used here).
 // Per stream, the order of frames is kept: a merge is enqueued only when no
-// other batch of that stream is in flight, and no frame of the stream is
-// scheduled while its merge is in flight.  Every result is therefore the
-// same whether a stream is served alone or in the mix.
+// other batch of that stream is in flight, it is the stream's last frame in
+// its batch, and no frame of the stream is scheduled while its merge is in
+// flight.  Every result is therefore the same whether a stream is served
+// alone or in the mix.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
