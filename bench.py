@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--serve-capacity-seconds", type=float, default=10.0,
                    help="seconds of arrivals offered all at once to measure the served capacity")
     p.add_argument("--serve-budget-gib", type=float, default=32.0)
+    p.add_argument("--serve-inflight", type=int, default=3, help="batches on the device at once (served)")
+    p.add_argument("--serve-batch", type=int, default=256, help="most frames per batch (served)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="time budget of the oracle's timed sample (all training frames, then test frames)")
@@ -312,7 +314,7 @@ def run_served(a):
         masks = ([np.zeros((wmax, specs[small].height, (specs[small].width + 63) // 64), dtype=np.uint64)]
                  if watch else [])
         st = obg.obg_serve_run(streams, arr, ctx.fn, ctx.ctx, speed=speed, budget_bytes=budget,
-                               max_inflight=3, max_batch_frames=256, remerge_period=period,
+                               max_inflight=a.serve_inflight, max_batch_frames=a.serve_batch, remerge_period=period,
                                remerge_window=window, checksums=sums,
                                watch=[small] if watch else None, watch_masks=masks,
                                watch_max_frames=wmax if watch else 0)
@@ -358,7 +360,7 @@ def run_served(a):
                    "fps_range": [5, 30], "offered_gpixel_s": round(sum(r * sp.width * sp.height for r, sp in
                                                                        zip(rates, specs)) / 1e9, 3),
                    "budget_gib": a.serve_budget_gib, "remerge_period": period, "remerge_window": window,
-                   "max_inflight_batches": 3, "max_batch_frames": 256},
+                   "max_inflight_batches": a.serve_inflight, "max_batch_frames": a.serve_batch},
         "capacity": {"simulated_s": a.serve_capacity_seconds, "frames": cap["frames_served"],
                      "gpixel": round(cap_px / 1e9, 2), "wall_s": round(cap["wall_s"], 3),
                      "gpixel_s": round(cap_px / cap["wall_s"] / 1e9, 2),

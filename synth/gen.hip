@@ -36,137 +36,138 @@ struct StreamConst {
 // frame record: [0] frame index, [1] frame hash, [2] drift scale (Q16),
 // [3] number of objects, then per object: kind (0 rect, 1 ellipse), x, y, a,
 // b, R, G, B
-__global__ void gen_kernel(StreamConst sc, const int32_t *__restrict__ recs, int n_frames,
-                           const int16_t *__restrict__ ntab, uint8_t *__restrict__ out) {
-    const int64_t npx = (int64_t)sc.width * sc.height;
-    const int fi = blockIdx.y;
-    if (fi >= n_frames) return;
-    const int32_t *r = recs + (int64_t)fi * kFrameInts;
+// The 16 pixels x0 = 16*gx .. x0+15 of row y of one frame (fewer at the row
+// end), written as 48 bytes with three 16-byte stores when the group is whole.
+__device__ __forceinline__ void gen_group(const StreamConst &sc, const int32_t *__restrict__ r,
+                                          const int16_t *__restrict__ ntab, uint8_t *__restrict__ fo, int y,
+                                          int gx) {
     const int f = r[0];
     const uint32_t hf = (uint32_t)r[1];
     const int32_t scale = r[2];
     const int nobj = r[3];
-    uint8_t *fo = out + (int64_t)fi * sc.frame_pitch;
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npx; p += (int64_t)gridDim.x * blockDim.x) {
-        const int y = (int)(p / sc.width), x = (int)(p - (int64_t)y * sc.width);
-        const uint32_t pix = (uint32_t)p;
-        const uint32_t base = fmix32(pix ^ hf);
-        const uint32_t u = base & 0xFFFFu;
-        uint32_t ci = (u >= sc.t0) + (u >= sc.t1) + (u >= sc.t2);
-        if (sc.bimodal) {
-            const uint32_t hb = fmix32(pix ^ sc.kb);
-            if (hb < sc.bthr) {
-                const uint32_t phase = fmix32(hb ^ 0x5851F42Du) % (uint32_t)sc.period;
-                ci = ((uint32_t)(f + phase) % (uint32_t)sc.period >= 4u) ? 1u : 0u;
+    const int x0 = gx * 16;
+    const int nv = min(16, sc.width - x0);
+    const int nbx = (sc.width + sc.block - 1) / sc.block;
+    const uint32_t prow = (uint32_t)y * (uint32_t)sc.width;
+    const uint32_t brow = (uint32_t)(y / sc.block) * (uint32_t)nbx;
+    int bx = x0 / sc.block, br = x0 - bx * sc.block;
+    // objects that reach this row
+    uint32_t rowhit = 0;
+    for (int o = 0; o < nobj; ++o) {
+        const int32_t *ob = r + 4 + 8 * o;
+        const int py = ob[2], b = ob[4];
+        const bool hit = ob[0] == 0 ? (y >= py && y < py + b) : (y - py <= b && py - y <= b);
+        rowhit |= (hit ? 1u : 0u) << o;
+    }
+    uint32_t w[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) w[k] = 0;
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+        if (p < nv) {
+            const int x = x0 + p;
+            const uint32_t pix = prow + (uint32_t)x;
+            const uint32_t base = fmix32(pix ^ hf);
+            const uint32_t u = base & 0xFFFFu;
+            uint32_t ci = (u >= sc.t0) + (u >= sc.t1) + (u >= sc.t2);
+            if (sc.bimodal) {
+                const uint32_t hb = fmix32(pix ^ sc.kb);
+                if (hb < sc.bthr) {
+                    const uint32_t phase = fmix32(hb ^ 0x5851F42Du) % (uint32_t)sc.period;
+                    ci = ((uint32_t)(f + phase) % (uint32_t)sc.period >= 4u) ? 1u : 0u;
+                }
             }
-        }
-        const int nbx = (sc.width + sc.block - 1) / sc.block;
-        const uint32_t idx = (uint32_t)(((y / sc.block) * nbx + x / sc.block) * sc.n_palette) + ci;
-        uint32_t h = fmix32(idx ^ sc.kp);
-        h = fmix32(h + 0x632BE5ABu);
-        int c[3] = {(int)(h & 255u), (int)((h >> 8) & 255u), (int)((h >> 16) & 255u)};
-        if (scale != 65536) {
-            for (int k = 0; k < 3; ++k) {
-                const int64_t v = ((int64_t)c[k] * scale + 32768) >> 16;
-                c[k] = (int)(v > 255 ? 255 : v);
+            const uint32_t idx = (brow + (uint32_t)bx) * (uint32_t)sc.n_palette + ci;
+            uint32_t h = fmix32(idx ^ sc.kp);
+            h = fmix32(h + 0x632BE5ABu);
+            int c0 = (int)(h & 255u), c1 = (int)((h >> 8) & 255u), c2 = (int)((h >> 16) & 255u);
+            if (scale != 65536) {
+                c0 = min((c0 * scale + 32768) >> 16, 255);
+                c1 = min((c1 * scale + 32768) >> 16, 255);
+                c2 = min((c2 * scale + 32768) >> 16, 255);
             }
-        }
-        const uint32_t h2 = fmix32(base ^ 0x68E31DA4u);
-        const uint32_t h3 = fmix32(base ^ 0xB5297A4Du);
-        const int n[3] = {ntab[h2 & 0xFFFFu], ntab[h2 >> 16], ntab[h3 & 0xFFFFu]};
-        for (int k = 0; k < 3; ++k) {
-            int v = c[k] + n[k];
-            c[k] = v < 0 ? 0 : (v > 255 ? 255 : v);
-        }
-        for (int o = 0; o < nobj; ++o) {
-            const int32_t *ob = r + 4 + 8 * o;
-            const int64_t px = ob[1], py = ob[2], a = ob[3], b = ob[4];
-            bool in;
-            if (ob[0] == 0) {
-                in = x >= px && x < px + a && y >= py && y < py + b;
-            } else {
-                const int64_t dx = (x - px) * b, dy = (y - py) * a;
-                in = dx * dx + dy * dy <= (a * b) * (a * b);
+            const uint32_t h2 = fmix32(base ^ 0x68E31DA4u);
+            const uint32_t h3 = fmix32(base ^ 0xB5297A4Du);
+            c0 = min(max(c0 + (int)ntab[h2 & 0xFFFFu], 0), 255);
+            c1 = min(max(c1 + (int)ntab[h2 >> 16], 0), 255);
+            c2 = min(max(c2 + (int)ntab[h3 & 0xFFFFu], 0), 255);
+            for (uint32_t m = rowhit; m; m &= m - 1) {
+                const int32_t *ob = r + 4 + 8 * __builtin_ctz(m);
+                const int px = ob[1], py = ob[2], a = ob[3], b = ob[4];
+                bool in;
+                if (ob[0] == 0) {
+                    in = x >= px && x < px + a;
+                } else if (x - px > a || px - x > a) {
+                    in = false;
+                } else {
+                    const int64_t dx = (int64_t)(x - px) * b, dy = (int64_t)(y - py) * a;
+                    const int64_t ab = (int64_t)a * b;
+                    in = dx * dx + dy * dy <= ab * ab;
+                }
+                if (in) {
+                    c0 = ob[5];
+                    c1 = ob[6];
+                    c2 = ob[7];
+                }
             }
-            if (in) { c[0] = ob[5]; c[1] = ob[6]; c[2] = ob[7]; }
+            const uint32_t v = (uint32_t)c0 | ((uint32_t)c1 << 8) | ((uint32_t)c2 << 16);
+            // bytes 3p .. 3p+2 of the group
+            const int b0 = 3 * p, k0 = b0 >> 2, s0 = (b0 & 3) * 8;   // constants once unrolled
+            w[k0] |= v << s0;
+            if (s0 > 8) w[k0 + 1] |= v >> (32 - s0);
         }
-        uint8_t *q = fo + (int64_t)y * sc.row_pitch + 3 * x;
-        q[0] = (uint8_t)c[0];
-        q[1] = (uint8_t)c[1];
-        q[2] = (uint8_t)c[2];
+        if (++br == sc.block) {
+            br = 0;
+            ++bx;
+        }
+    }
+    uint8_t *q = fo + (int64_t)y * sc.row_pitch + 48 * (int64_t)gx;
+    if (nv == 16) {
+        uint4 *q4 = reinterpret_cast<uint4 *>(q);
+        q4[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        q4[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        q4[2] = make_uint4(w[8], w[9], w[10], w[11]);
+    } else {
+        for (int bidx = 0; bidx < 3 * nv; ++bidx) q[bidx] = (uint8_t)(w[bidx >> 2] >> ((bidx & 3) * 8));
     }
 }
 
-// One frame of a batch of frames from many streams.
+// One stream, several frames: blockIdx.y = frame of `recs`.
+__global__ __launch_bounds__(256) void gen_kernel(StreamConst sc, const int32_t *__restrict__ recs, int n_frames,
+                                                  const int16_t *__restrict__ ntab, uint8_t *__restrict__ out) {
+    const int fi = blockIdx.y;
+    if (fi >= n_frames) return;
+    const int ngx = (sc.width + 15) / 16;
+    const uint32_t groups = (uint32_t)sc.height * (uint32_t)ngx;
+    const int32_t *r = recs + (int64_t)fi * kFrameInts;
+    uint8_t *fo = out + (int64_t)fi * sc.frame_pitch;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += gridDim.x * blockDim.x) {
+        const int y = (int)(g / (uint32_t)ngx);
+        gen_group(sc, r, ntab, fo, y, (int)(g - (uint32_t)y * ngx));
+    }
+}
+
 struct IngestJob {
     StreamConst sc;
     const int32_t *rec;
     uint8_t *out;
 };
 
-__global__ void gen_batch_kernel(const IngestJob *__restrict__ jobs, int n_jobs, const int16_t *__restrict__ ntab) {
+// Frames of many streams: blockIdx.y = job.
+__global__ __launch_bounds__(256) void gen_batch_kernel(const IngestJob *__restrict__ jobs, int n_jobs,
+                                                        const int16_t *__restrict__ ntab) {
     const int j = blockIdx.y;
     if (j >= n_jobs) return;
-    const IngestJob job = jobs[j];
-    const StreamConst &sc = job.sc;
-    const int64_t npx = (int64_t)sc.width * sc.height;
-    const int32_t *r = job.rec;
-    const int f = r[0];
-    const uint32_t hf = (uint32_t)r[1];
-    const int32_t scale = r[2];
-    const int nobj = r[3];
-    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < npx; p += (int64_t)gridDim.x * blockDim.x) {
-        const int y = (int)(p / sc.width), x = (int)(p - (int64_t)y * sc.width);
-        const uint32_t pix = (uint32_t)p;
-        const uint32_t base = fmix32(pix ^ hf);
-        const uint32_t u = base & 0xFFFFu;
-        uint32_t ci = (u >= sc.t0) + (u >= sc.t1) + (u >= sc.t2);
-        if (sc.bimodal) {
-            const uint32_t hb = fmix32(pix ^ sc.kb);
-            if (hb < sc.bthr) {
-                const uint32_t phase = fmix32(hb ^ 0x5851F42Du) % (uint32_t)sc.period;
-                ci = ((uint32_t)(f + phase) % (uint32_t)sc.period >= 4u) ? 1u : 0u;
-            }
-        }
-        const int nbx = (sc.width + sc.block - 1) / sc.block;
-        const uint32_t idx = (uint32_t)(((y / sc.block) * nbx + x / sc.block) * sc.n_palette) + ci;
-        uint32_t h = fmix32(idx ^ sc.kp);
-        h = fmix32(h + 0x632BE5ABu);
-        int c[3] = {(int)(h & 255u), (int)((h >> 8) & 255u), (int)((h >> 16) & 255u)};
-        if (scale != 65536) {
-            for (int k = 0; k < 3; ++k) {
-                const int64_t v = ((int64_t)c[k] * scale + 32768) >> 16;
-                c[k] = (int)(v > 255 ? 255 : v);
-            }
-        }
-        const uint32_t h2 = fmix32(base ^ 0x68E31DA4u);
-        const uint32_t h3 = fmix32(base ^ 0xB5297A4Du);
-        const int n[3] = {ntab[h2 & 0xFFFFu], ntab[h2 >> 16], ntab[h3 & 0xFFFFu]};
-        for (int k = 0; k < 3; ++k) {
-            int v = c[k] + n[k];
-            c[k] = v < 0 ? 0 : (v > 255 ? 255 : v);
-        }
-        for (int o = 0; o < nobj; ++o) {
-            const int32_t *ob = r + 4 + 8 * o;
-            const int64_t px = ob[1], py = ob[2], a = ob[3], b = ob[4];
-            bool in;
-            if (ob[0] == 0) {
-                in = x >= px && x < px + a && y >= py && y < py + b;
-            } else {
-                const int64_t dx = (x - px) * b, dy = (y - py) * a;
-                in = dx * dx + dy * dy <= (a * b) * (a * b);
-            }
-            if (in) { c[0] = ob[5]; c[1] = ob[6]; c[2] = ob[7]; }
-        }
-        uint8_t *q = job.out + (int64_t)y * sc.row_pitch + 3 * x;
-        q[0] = (uint8_t)c[0];
-        q[1] = (uint8_t)c[1];
-        q[2] = (uint8_t)c[2];
+    const IngestJob &job = jobs[j];
+    const StreamConst sc = job.sc;
+    const int ngx = (sc.width + 15) / 16;
+    const uint32_t groups = (uint32_t)sc.height * (uint32_t)ngx;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += gridDim.x * blockDim.x) {
+        const int y = (int)(g / (uint32_t)ngx);
+        gen_group(sc, job.rec, ntab, job.out, y, (int)(g - (uint32_t)y * ngx));
     }
 }
 
-// Ingest context for a serving run: every stream's constants and the frame
-// records of every frame that may arrive, resident on the device.
 struct IngestCtx {
     int n_streams;
     StreamConst *consts;         // host copy
@@ -176,6 +177,8 @@ struct IngestCtx {
     const int16_t *d_ntab;
     IngestJob *h_jobs;           // pinned staging, one slot of kMaxJobs per in-flight batch
     IngestJob *d_jobs;
+    hipEvent_t *slot_done;       // per slot: its last use has run on the device
+    bool *slot_used;
     int slots, next_slot;
 };
 
@@ -189,6 +192,8 @@ struct SynthIngestItem {
     int32_t frame;
     uint8_t *dst;
 };
+
+extern "C" void synth_ingest_destroy(void *ctx);
 
 extern "C" void *synth_ingest_create(int32_t n_streams, const int32_t *params, const int32_t *d_recs,
                                      const int64_t *rec_base, const int32_t *n_recs, const int16_t *d_ntab,
@@ -213,9 +218,14 @@ extern "C" void *synth_ingest_create(int32_t n_streams, const int32_t *params, c
     c->d_ntab = d_ntab;
     c->slots = slots;
     c->next_slot = 0;
-    if (hipHostMalloc((void **)&c->h_jobs, sizeof(IngestJob) * kMaxJobs * slots, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void **)&c->d_jobs, sizeof(IngestJob) * kMaxJobs * slots) != hipSuccess) {
-        delete[] c->consts; delete[] c->rec_base; delete[] c->n_recs; delete c;
+    c->slot_done = new hipEvent_t[slots]();
+    c->slot_used = new bool[slots]();
+    bool ok = hipHostMalloc((void **)&c->h_jobs, sizeof(IngestJob) * kMaxJobs * slots, hipHostMallocDefault) == hipSuccess &&
+              hipMalloc((void **)&c->d_jobs, sizeof(IngestJob) * kMaxJobs * slots) == hipSuccess;
+    for (int i = 0; ok && i < slots; ++i)
+        ok = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+        synth_ingest_destroy(c);
         return nullptr;
     }
     return c;
@@ -224,27 +234,37 @@ extern "C" void *synth_ingest_create(int32_t n_streams, const int32_t *params, c
 extern "C" void synth_ingest_destroy(void *ctx) {
     IngestCtx *c = (IngestCtx *)ctx;
     if (!c) return;
-    hipHostFree(c->h_jobs);
-    hipFree(c->d_jobs);
+    for (int i = 0; i < c->slots; ++i)
+        if (c->slot_done && c->slot_done[i]) {
+            (void)hipEventSynchronize(c->slot_done[i]);
+            (void)hipEventDestroy(c->slot_done[i]);
+        }
+    if (c->h_jobs) (void)hipHostFree(c->h_jobs);
+    if (c->d_jobs) (void)hipFree(c->d_jobs);
+    delete[] c->slot_done;
+    delete[] c->slot_used;
     delete[] c->consts; delete[] c->rec_base; delete[] c->n_recs;
     delete c;
 }
 
 // Generate the listed frames into their device buffers, enqueued on `stream`.
-// The staging slots rotate; a slot is reused only after `slots` later calls,
-// so the caller keeps at most `slots` calls in flight.
+// The staging slots rotate; before a slot is refilled, the host waits until
+// the work of its previous use has run, so calls may finish in any order.
 extern "C" int synth_ingest(void *ctx, const SynthIngestItem *items, int32_t n, hipStream_t stream) {
     IngestCtx *c = (IngestCtx *)ctx;
     if (!c || n < 0 || n > kMaxJobs) return -1;
     if (n == 0) return 0;
     const int slot = c->next_slot;
     c->next_slot = (c->next_slot + 1) % c->slots;
+    if (c->slot_used[slot] && hipEventSynchronize(c->slot_done[slot]) != hipSuccess) return -3;
     IngestJob *hj = c->h_jobs + (size_t)slot * kMaxJobs;
     IngestJob *dj = c->d_jobs + (size_t)slot * kMaxJobs;
     int64_t maxpx = 0;
     for (int i = 0; i < n; ++i) {
         const int s = items[i].stream, f = items[i].frame;
-        if (s < 0 || s >= c->n_streams || f < 0 || f >= c->n_recs[s] || !items[i].dst) return -1;
+        if (s < 0 || s >= c->n_streams || f < 0 || f >= c->n_recs[s] || !items[i].dst ||
+            (uintptr_t)items[i].dst % 16 || c->consts[s].row_pitch % 16)
+            return -1;
         hj[i].sc = c->consts[s];
         hj[i].rec = c->d_recs + (c->rec_base[s] + f) * kFrameInts;
         hj[i].out = items[i].dst;
@@ -252,10 +272,13 @@ extern "C" int synth_ingest(void *ctx, const SynthIngestItem *items, int32_t n, 
         if (px > maxpx) maxpx = px;
     }
     if (hipMemcpyAsync(dj, hj, sizeof(IngestJob) * n, hipMemcpyHostToDevice, stream) != hipSuccess) return -3;
-    int gx = (int)((maxpx + 255) / 256);
+    int gx = (int)((maxpx / 16 + 255) / 256);
     if (gx > 1024) gx = 1024;
+    if (gx < 1) gx = 1;
     hipLaunchKernelGGL(gen_batch_kernel, dim3(gx, n), dim3(256), 0, stream, (const IngestJob *)dj, n, c->d_ntab);
-    return hipGetLastError() == hipSuccess ? 0 : -3;
+    if (hipGetLastError() != hipSuccess || hipEventRecord(c->slot_done[slot], stream) != hipSuccess) return -3;
+    c->slot_used[slot] = true;
+    return 0;
 }
 
 extern "C" int synth_generate(int32_t width, int32_t height, int64_t row_pitch, int64_t frame_pitch,
@@ -266,11 +289,12 @@ extern "C" int synth_generate(int32_t width, int32_t height, int64_t row_pitch, 
     if (width < 1 || height < 1 || n_frames < 0 || row_pitch < 3LL * width || frame_pitch < height * row_pitch)
         return -1;
     if (!recs || !ntab || !out || period < 1 || block < 1 || n_palette < 1) return -1;
+    if (row_pitch % 16 || frame_pitch % 16 || (uintptr_t)out % 16) return -1;   // 16-byte stores
     if (n_frames == 0) return 0;
     if ((int64_t)width * height > 0xFFFFFFFFLL || n_frames > 65535) return -1;
     StreamConst sc{width, height, row_pitch, frame_pitch, kp, kb, bthr, bimodal, period, block, n_palette, t0, t1, t2};
-    const int64_t npx = (int64_t)width * height;
-    int gx = (int)((npx + 255) / 256);
+    const int64_t groups = (int64_t)height * ((width + 15) / 16);
+    int gx = (int)((groups + 255) / 256);
     if (gx > 4096) gx = 4096;
     hipLaunchKernelGGL(gen_kernel, dim3(gx, n_frames), dim3(256), 0, stream, sc, recs, n_frames, ntab, out);
     return hipGetLastError() == hipSuccess ? 0 : -3;

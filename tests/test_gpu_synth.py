@@ -18,6 +18,11 @@ def test_fast_generator_matches_definition(fast):
     specs = [F.cfg0().streams[0], F.cfg1(n_test=3).streams[0]]
     specs += F.mixed_streams(6, seed=9, n_test=4)[0]
     specs.append(F.StreamSpec(100, 37, 2, 3, seed=4, fg="ellipses", fg_coverage=0.2, drift_amp=0.3, bimodal_frac=0.5))
+    # widths that end in a partial 16-pixel group, and narrower than one group
+    for W, H in [(33, 17), (7, 5), (16, 3), (47, 2), (1, 1)]:
+        specs.append(F.StreamSpec(W, H, 2, 3, seed=6, fg="ellipses", fg_coverage=0.3, drift_amp=0.2,
+                                  bimodal_frac=0.3, block=5))
+    specs.append(F.StreamSpec(70, 20, 2, 3, seed=7, fg="rect", rect_size=9))
     for spec in specs:
         ids = [0, 1, spec.n_train, spec.n_frames - 1]
         print(f"[case] {spec.width}x{spec.height} frames {ids}", flush=True)
