@@ -485,6 +485,21 @@ def main():
     cls_ms = sorted(e[0].elapsed_time(e[1]) for e in evs)
     cls_avg = sum(cls_ms) / len(cls_ms)
 
+    # the merge alone, and over trees of groups of 5 frames (Section 3)
+    def time_merge(group, reps=20):
+        leaf_g = obg.empty_leafset(g)
+        ts = []
+        for r in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            obg.obg_merge_groups(g, occ, T, 0, T, group, num, den, leaf_g)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if r:
+                ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2]
+    merge_ms, merge_g5_ms = time_merge(1), time_merge(5)
+
     # the fused pass of the serving path: mask and the frame's occupancy in one read
     occ_t = obg.empty_occ(g, N)
     mask_f = obg.empty_mask(g, N)
@@ -535,6 +550,8 @@ def main():
         "classify": {"ms_avg": round(cls_avg, 4), "ms_p50": round(cls_ms[len(cls_ms) // 2], 4),
                      "gpixel_s": round(N * spec.pixels / (cls_avg * 1e-3) / 1e9, 3)},
         "train_merge_ms": round(ms_step - cls_avg, 4),
+        "merge": {"ms_p50": round(merge_ms, 4), "groups_of_5_ms_p50": round(merge_g5_ms, 4),
+                  "bitset_bytes_read": T * g.n_regions * g.words * 4},
         "classify_occ": {"ms_avg": round(fused_ms, 4),
                          "gpixel_s": round(N * spec.pixels / (fused_ms * 1e-3) / 1e9, 3),
                          "tb_s": round((cls_bytes + occ_bytes) / (fused_ms * 1e-3) / 1e12, 3),

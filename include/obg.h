@@ -96,8 +96,9 @@ int obg_train_frame(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
 /*
  * Merge of per-frame trees (Algorithm 2).  A path key k of region r is kept
  * iff C = number of trees in the window whose bitset has k satisfies
- * C * thr_den >= thr_num * n_trees (the paper's count/numberOfTrees >=
- * threshold, done exactly in integers).  Because every tree that holds a
+ * C * thr_den >= thr_num * n_trees (the paper compares the fraction of trees
+ * holding the path with the threshold; here the comparison is exact in
+ * integers).  Because every tree that holds a
  * path also holds all its prefixes, this per-key test gives the same depth-d
  * nodes as the paper's level-by-level recursion.
  *   occ_ring : [ring_len][n_regions][ceil(8^d/32)] uint32, per-frame bitsets.
@@ -112,6 +113,20 @@ int obg_train_frame(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
 int obg_merge(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len,
               int32_t first, int32_t n_trees, uint32_t thr_num, uint32_t thr_den,
               uint32_t *leafset, hipStream_t stream);
+
+/*
+ * Merge of trees built from groups of frames (Section 3 allows one tree per
+ * frame or per group of frames).  The window's n_trees slots are taken in
+ * groups of `group` consecutive slots, the last group possibly shorter; a
+ * group's tree holds every colour of its frames, so its bitset is the OR of
+ * the group's bitsets.  Key k is kept iff G * thr_den >= thr_num * n_groups,
+ * G = number of groups holding k, n_groups = ceil(n_trees / group).
+ * group = 1 is obg_merge.  Arguments and errors as obg_merge, and EINVAL for
+ * group < 1.
+ */
+int obg_merge_groups(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len, int32_t first,
+                     int32_t n_trees, int32_t group, uint32_t thr_num, uint32_t thr_den, uint32_t *leafset,
+                     hipStream_t stream);
 
 /*
  * Foreground detection (Algorithm 3 for every pixel, Section 4): mask bit 1

@@ -43,6 +43,7 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "orc_forest_new": (_P, [_I, _I, _I, _I, _I]),
         "orc_forest_regions": (_I, [_P]),
         "orc_forest_add_frame": (_I, [_P, _P, _I64, _I]),
+        "orc_forest_add_group": (_I, [_P, _P, _I, _I64, _I]),
         "orc_forest_add_occupancy": (_I, [_P, _P]),
         "orc_forest_frame_export": (_I, [_P, _I, _P, _P]),
         "orc_forest_frame_nodes": (_I64, [_P, _I]),
@@ -114,6 +115,19 @@ class Forest:
 
     def add_frames(self, frames: Iterable[np.ndarray], store_levels=None):
         return [self.add_frame(f, store_levels) for f in frames]
+
+    def add_group(self, frames: Sequence[np.ndarray], store_levels: Optional[int] = None) -> int:
+        """One tree (per region) holding the colours of every frame of the group."""
+        fs = [np.ascontiguousarray(f, dtype=np.uint8) for f in frames]
+        assert fs and all(f.shape == fs[0].shape for f in fs)
+        assert fs[0].ndim == 2 and fs[0].shape[0] == self.height and fs[0].shape[1] >= 3 * self.width
+        lv = self.depth if store_levels is None else store_levels
+        ptrs = (ctypes.c_void_p * len(fs))(*[f.ctypes.data for f in fs])
+        i = self.lib.orc_forest_add_group(self.h, ptrs, len(fs), fs[0].shape[1], lv)
+        if i < 0:
+            raise ValueError("oracle: bad group")
+        self.n += 1
+        return i
 
     def add_occupancy(self, occ: np.ndarray) -> int:
         occ = np.ascontiguousarray(occ, dtype=np.uint32).reshape(self.n_regions, leaf_words(self.depth))

@@ -17,6 +17,8 @@
  *   - merge_into    : Algorithm 2 (Merge Trees), recursive, Section 3.
  *   - check_color   : Algorithm 3 (Check Color), Section 4.
  *   - regions       : one tree per spatial region, Sections 3 and 4.
+ *   - add_group     : one tree holding the colours of a group of frames
+ *                     (Section 3 allows a tree per frame or per group).
  *
  * Readings of points the paper leaves open (each one is listed with its
  * justification in the design notes of the repository):
@@ -376,25 +378,33 @@ static int forest_append(Forest *f, Trees *t) {
     return f->nframes++;
 }
 
-/* Build one frame's trees: Store Color of every pixel into its region's tree
- * at `store_levels` levels, then prune each tree to the kept depth. */
-int orc_forest_add_frame(Forest *f, const uint8_t *rgb, int64_t row_pitch, int store_levels) {
+/* Build the trees of a group of frames: Store Color of every pixel of every
+ * frame of the group into its region's tree at `store_levels` levels, then
+ * prune each tree to the kept depth.  A group of one frame is a frame's tree;
+ * Section 3 allows a tree per frame or per group of frames. */
+static int add_group(Forest *f, const uint8_t *const *frames, int n, int64_t row_pitch, int store_levels) {
     const Geom *g = &f->g;
-    if (store_levels < g->depth || store_levels > 8) return -1;
+    if (store_levels < g->depth || store_levels > 8 || n < 1) return -1;
     int nreg = geom_regions(g);
     Trees *full = trees_new(nreg);
     Trees *pruned = trees_new(nreg);
-    /* one tree per region, built from that region's pixels (Section 3) */
-    for (int ry = 0; ry < g->reg_rows; ++ry) {
-        for (int rx = 0; rx < g->reg_cols; ++rx) {
-            const int y0 = ry * g->region_h, x0 = rx * g->region_w;
-            const int y1 = y0 + g->region_h < g->height ? y0 + g->region_h : g->height;
-            const int x1 = x0 + g->region_w < g->width ? x0 + g->region_w : g->width;
-            for (int y = y0; y < y1; ++y) {
-                const uint8_t *row = rgb + (int64_t)y * row_pitch;
-                for (int x = x0; x < x1; ++x) {
-                    const uint8_t *p = row + 3 * x;
-                    store_color(&full->roots[region_of(g, x, y)], &full->arena, p[0], p[1], p[2], store_levels);
+#if ORC_MUTANT == 10  /* a group's tree built from its first frame only */
+    n = 1;
+#endif
+    for (int j = 0; j < n; ++j) {
+        const uint8_t *rgb = frames[j];
+        /* one tree per region, built from that region's pixels (Section 3) */
+        for (int ry = 0; ry < g->reg_rows; ++ry) {
+            for (int rx = 0; rx < g->reg_cols; ++rx) {
+                const int y0 = ry * g->region_h, x0 = rx * g->region_w;
+                const int y1 = y0 + g->region_h < g->height ? y0 + g->region_h : g->height;
+                const int x1 = x0 + g->region_w < g->width ? x0 + g->region_w : g->width;
+                for (int y = y0; y < y1; ++y) {
+                    const uint8_t *row = rgb + (int64_t)y * row_pitch;
+                    for (int x = x0; x < x1; ++x) {
+                        const uint8_t *p = row + 3 * x;
+                        store_color(&full->roots[region_of(g, x, y)], &full->arena, p[0], p[1], p[2], store_levels);
+                    }
                 }
             }
         }
@@ -408,6 +418,16 @@ int orc_forest_add_frame(Forest *f, const uint8_t *rgb, int64_t row_pitch, int s
     }
     trees_free(full);
     return forest_append(f, pruned);
+}
+
+/* One frame's trees. */
+int orc_forest_add_frame(Forest *f, const uint8_t *rgb, int64_t row_pitch, int store_levels) {
+    return add_group(f, &rgb, 1, row_pitch, store_levels);
+}
+
+/* The trees of a group of n frames (all with the same row pitch). */
+int orc_forest_add_group(Forest *f, const uint8_t *const *frames, int n, int64_t row_pitch, int store_levels) {
+    return add_group(f, frames, n, row_pitch, store_levels);
 }
 
 /* Build a frame's trees from an occupancy bitset [n_regions][words]: every

@@ -286,9 +286,9 @@ int obg_train_frame(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, uin
     return run_pixels(o, mode, rgb, n_frames, nullptr, nullptr, occ, counts, stream);
 }
 
-int obg_merge(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len, int32_t first,
-              int32_t n_trees, uint32_t thr_num, uint32_t thr_den, uint32_t *leafset,
-              hipStream_t stream) {
+int obg_merge_groups(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len, int32_t first,
+                     int32_t n_trees, int32_t group, uint32_t thr_num, uint32_t thr_den, uint32_t *leafset,
+                     hipStream_t stream) {
     Geo o;
     int rc = check_geom(g, &o, false);
     if (rc) return rc;
@@ -297,27 +297,36 @@ int obg_merge(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len, int
     if (n_trees > 65535) return fail(OBG_EINVAL, "n_trees must be <= 65535 (got %d)", n_trees);
     if (ring_len < n_trees) return fail(OBG_EINVAL, "ring_len %d < n_trees %d", ring_len, n_trees);
     if (first < 0 || first >= ring_len) return fail(OBG_EINVAL, "first %d outside [0, ring_len)", first);
+    if (group < 1) return fail(OBG_EINVAL, "group must be >= 1 (got %d)", group);
     if (thr_num == 0) return fail(OBG_EINVAL, "thr_num must be >= 1 (a zero threshold keeps paths no tree has)");
     if (thr_den == 0) return fail(OBG_EINVAL, "thr_den must be >= 1");
-    // smallest count C with C * den >= num * n_trees
-    const uint64_t need = (uint64_t)thr_num * (uint64_t)n_trees;
+    const int32_t n_groups = (n_trees + group - 1) / group;
+    // smallest count C with C * den >= num * n_groups
+    const uint64_t need = (uint64_t)thr_num * (uint64_t)n_groups;
     const uint64_t kmin = (need + thr_den - 1) / thr_den;
     MergeArgs a{};
     a.occ_ring = occ_ring;
     a.ring_len = ring_len;
     a.first = first;
     a.n_trees = n_trees;
+    a.group = group;
     a.slot_words = (int64_t)o.n_regions * o.words;
     a.words = o.words;
     a.valid_bits_last = leaf_count(o.depth) < 32 ? leaf_count(o.depth) : 32;
-    a.empty = kmin > (uint64_t)n_trees ? 1 : 0;
+    a.empty = kmin > (uint64_t)n_groups ? 1 : 0;
     a.kmin = a.empty ? 0u : (uint32_t)kmin;
     a.leaf = leafset;
     a.planes = 0;
-    while ((1 << a.planes) <= n_trees) ++a.planes;
+    while ((1 << a.planes) <= n_groups) ++a.planes;
     hipError_t e = launch_merge(a, stream);
     if (e != hipSuccess) return hip_fail(e, "merge kernel launch");
     return OBG_OK;
+}
+
+int obg_merge(const obg_geom *g, const uint32_t *occ_ring, int32_t ring_len, int32_t first,
+              int32_t n_trees, uint32_t thr_num, uint32_t thr_den, uint32_t *leafset,
+              hipStream_t stream) {
+    return obg_merge_groups(g, occ_ring, ring_len, first, n_trees, 1, thr_num, thr_den, leafset, stream);
 }
 
 int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, const uint32_t *leafset,

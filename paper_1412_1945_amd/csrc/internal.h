@@ -56,6 +56,7 @@ struct MergeArgs {
     int32_t planes;           // counter bit planes: bit length of n_trees
     int32_t empty;            // kmin > n_trees: nothing kept
     uint32_t *leaf;
+    int32_t group;            // window slots per counted tree (1 = one tree per frame)
 };
 
 enum StripMode { MODE_MASK = 1, MODE_OCC = 2, MODE_COUNTS = 4 };

@@ -149,7 +149,7 @@ __global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= a.slot_words) return;
     a.leaf[i] = merge_word(a.occ_ring, a.ring_len, a.first, a.n_trees, a.slot_words, i,
-                           a.valid_bits_last, a.kmin, a.planes, a.empty);
+                           a.valid_bits_last, a.kmin, a.planes, a.empty, a.group);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -265,7 +265,8 @@ hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream) {
 }
 
 hipError_t launch_merge(const MergeArgs &a, hipStream_t stream) {
-    if (!a.occ_ring || !a.leaf || a.ring_len < 1 || a.first < 0 || a.first >= a.ring_len)
+    if (!a.occ_ring || !a.leaf || a.ring_len < 1 || a.first < 0 || a.first >= a.ring_len || a.group < 1 ||
+        a.n_trees < 1 || a.n_trees > a.ring_len)
         return hipErrorInvalidValue;
     if (a.slot_words == 0) return hipSuccess;
     const int block = 256;

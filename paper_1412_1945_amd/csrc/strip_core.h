@@ -213,30 +213,37 @@ __device__ __forceinline__ void span_loop(const StripArgs &a, __amdgpu_buffer_rs
 }
 
 // One merged word (32 keys) of Algorithm 2 in closed form: bit-sliced
-// counters of the window's bitsets, then a bit-sliced compare with kmin.
+// counters of the window's bitsets, then a bit-sliced compare with kmin.  With
+// group > 1 the window's trees are taken in groups of `group` consecutive
+// slots (the last may be shorter) and each group counts once, as the OR of its
+// trees (the tree of a group of frames, Section 3); n_trees is the window
+// length in slots.
 __device__ __forceinline__ uint32_t merge_word(const uint32_t *__restrict__ ring, int ring_len, int first,
                                                int n_trees, int64_t slot_words, int64_t i, int valid_bits,
-                                               uint32_t kmin, int planes, int empty) {
+                                               uint32_t kmin, int planes, int empty, int group = 1) {
     const uint32_t valid = valid_bits >= 32 ? 0xFFFFFFFFu : ((1u << valid_bits) - 1u);
     if (empty) return 0;
     uint32_t c[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b) c[b] = 0;
-    // eight window slots per round: their loads are independent and in flight together
-    int slot = first;
-    for (int t0 = 0; t0 < n_trees; t0 += 8) {
+    const int n_groups = (n_trees + group - 1) / group;
+    // eight groups per round: their loads are independent and in flight together
+    for (int j0 = 0; j0 < n_groups; j0 += 8) {
         uint32_t x[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             x[k] = 0;
-            if (t0 + k < n_trees) {
-                int sl = slot + k;
-                if (sl >= ring_len) sl -= ring_len;
-                x[k] = ring[(int64_t)sl * slot_words + i] & valid;
+            if (j0 + k < n_groups) {
+                const int tb = (j0 + k) * group;
+                const int te = min(tb + group, n_trees);
+                for (int t = tb; t < te; ++t) {
+                    int sl = first + t;
+                    if (sl >= ring_len) sl -= ring_len;
+                    x[k] |= ring[(int64_t)sl * slot_words + i];
+                }
+                x[k] &= valid;
             }
         }
-        slot += 8;
-        while (slot >= ring_len) slot -= ring_len;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             uint32_t carry = x[k];

@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
             "obg_mask_words": (I64, [G]),
             "obg_train_frame": (ctypes.c_int, [G, P, I32, P, P, P]),
             "obg_merge": (ctypes.c_int, [G, P, I32, I32, I32, U32, U32, P, P]),
+            "obg_merge_groups": (ctypes.c_int, [G, P, I32, I32, I32, I32, U32, U32, P, P]),
             "obg_classify": (ctypes.c_int, [G, P, I32, P, P, P, P]),
             "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
@@ -133,7 +134,7 @@ def load() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
-            "obg_merge", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_probe",
+            "obg_merge", "obg_merge_groups", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_probe",
             "obg_batch_create", "obg_batch_run", "obg_batch_info_get", "obg_batch_destroy",
             "obg_serve_run", "obg_last_error", "obg_version"]
 
@@ -233,6 +234,14 @@ def obg_merge(g: FrameGeom, occ_ring: torch.Tensor, ring_len: int, first: int, n
     _need(leafset, torch.int32, g.n_regions * g.words, "leafset")
     _check(load().obg_merge(ctypes.byref(g.c()), _ptr(occ_ring), ring_len, first, n_trees,
                             thr_num, thr_den, _ptr(leafset), _stream(stream)))
+
+
+def obg_merge_groups(g: FrameGeom, occ_ring: torch.Tensor, ring_len: int, first: int, n_trees: int, group: int,
+                     thr_num: int, thr_den: int, leafset: torch.Tensor, stream=None):
+    _need(occ_ring, torch.int32, ring_len * g.n_regions * g.words, "occ_ring")
+    _need(leafset, torch.int32, g.n_regions * g.words, "leafset")
+    _check(load().obg_merge_groups(ctypes.byref(g.c()), _ptr(occ_ring), ring_len, first, n_trees, group,
+                                   thr_num, thr_den, _ptr(leafset), _stream(stream)))
 
 
 def obg_classify(g: FrameGeom, rgb: torch.Tensor, n_frames: int, leafset: torch.Tensor,

@@ -52,6 +52,26 @@ def merged_sets(frames, width, height, depth, num, den, rw=0, rh=0):
     return out
 
 
+def grouped_sets(frames, group, width, height, depth, num, den, rw=0, rh=0):
+    """Per region: triples present in at least num/den of the groups of
+    `group` consecutive frames (the last group may be shorter); a group holds
+    a triple when any of its frames does."""
+    groups = [frames[i: i + group] for i in range(0, len(frames), group)]
+    per = []
+    for grp in groups:
+        sets = [frame_sets(f, width, height, depth, rw, rh) for f in grp]
+        per.append([set().union(*[s[r] for s in sets]) for r in range(len(sets[0]))])
+    G = len(groups)
+    out = []
+    for r in range(len(per[0])):
+        c = Counter()
+        for p in per:
+            for t in p[r]:
+                c[t] += 1
+        out.append({t for t, n in c.items() if n * den >= num * G})
+    return out
+
+
 def mask_bits(frame, kept, width, height, depth, rw=0, rh=0):
     """bool [H, W]: True where the pixel's triple is not in its region's set."""
     q = quantised(frame, width, depth)

@@ -110,6 +110,15 @@ def test_merge_rejects_bad_window(lib, args, code):
     assert rc == code, L.obg_last_error()
 
 
+def test_merge_groups_rejects_bad_group(lib):
+    L = _raw(lib)
+    g = _geom(lib)
+    assert L.obg_merge_groups(ctypes.byref(g), FAKE, 4, 0, 4, 0, 1, 2, FAKE, None) == -1
+    assert L.obg_merge_groups(ctypes.byref(g), FAKE, 4, 0, 4, -2, 1, 2, FAKE, None) == -1
+    assert L.obg_merge_groups(ctypes.byref(g), FAKE, 4, 0, 5, 2, 1, 2, FAKE, None) == -1   # window > ring
+    assert L.obg_merge_groups(ctypes.byref(g), FAKE, 4, 0, 4, 2, 0, 2, FAKE, None) == -1
+
+
 def test_classify_rejects_null(lib):
     L = _raw(lib)
     g = _geom(lib)

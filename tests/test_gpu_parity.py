@@ -157,6 +157,44 @@ def test_merge_ring_windows(env):
             assert np.array_equal(u32(leaf).reshape(want.shape), want)
 
 
+def test_merge_groups_of_frames(env):
+    """Trees of groups of consecutive frames (Section 3): the GPU merge of
+    grouped ring windows against the oracle's group trees built from the
+    frames, including a short last group and a window that wraps the ring."""
+    obg, O = env
+    rng = np.random.default_rng(91)
+    for W, H, d, rw, rh, T, grp, ring, first, num, den in [
+            (40, 12, 4, 0, 0, 9, 2, 9, 0, 1, 2), (40, 12, 4, 0, 0, 9, 4, 12, 7, 2, 3),
+            (33, 20, 5, 16, 8, 7, 3, 10, 5, 1, 2), (64, 8, 3, 0, 0, 6, 6, 6, 0, 1, 1),
+            (25, 9, 6, 0, 0, 8, 1, 8, 3, 1, 2), (48, 16, 2, 16, 16, 10, 3, 13, 11, 7, 10)]:
+        rp = ((3 * W + 15) // 16) * 16
+        frames = brute.tiny_frames(rng, T + 1, W, H, n_colours=int(rng.integers(4, 20)), row_pitch=rp)
+        g = obg.FrameGeom(W, H, d, region_w=rw, region_h=rh)
+        print(f"[case] grouped merge W={W} H={H} d={d} region={rw}x{rh} T={T} group={grp} ring={ring} "
+              f"first={first} thr={num}/{den}", flush=True)
+        dev = upload(frames, g.frame_pitch)
+        occ = obg.empty_occ(g, ring)
+        occ.zero_()
+        for t in range(T):                    # frame t's tree into ring slot first + t
+            obg.obg_train_frame(g, dev[t], 1, occ[(first + t) % ring])
+        leaf = obg.empty_leafset(g)
+        obg.obg_merge_groups(g, occ, ring, first, T, grp, num, den, leaf)
+        torch.cuda.synchronize()
+        f = O.Forest(W, H, d, rw, rh)
+        idx = [f.add_group(frames[i: min(i + grp, T)]) for i in range(0, T, grp)]
+        model = f.merge(idx, num, den)
+        assert np.array_equal(u32(leaf).reshape(model.leafset().shape), model.leafset())
+        if grp == 1:
+            plain = obg.empty_leafset(g)
+            obg.obg_merge(g, occ, ring, first, T, num, den, plain)
+            torch.cuda.synchronize()
+            assert torch.equal(plain, leaf)
+        mask = obg.empty_mask(g, 1)
+        obg.obg_classify(g, dev[T], 1, leaf, mask)
+        torch.cuda.synchronize()
+        assert np.array_equal(u64(mask[0]), model.classify(frames[T]))
+
+
 def test_fused_classify_occupancy(env):
     obg, O = env
     rng = np.random.default_rng(3)

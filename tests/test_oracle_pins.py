@@ -103,6 +103,38 @@ def check_brute(O, seed, mutant=0, store_levels=8, regions=(0, 0)):
             assert np.array_equal(got, brute.mask_bits(fr, kept, W, H, d, rw, rh)), trial
 
 
+def check_groups(O, seed, mutant=0):
+    """Trees of groups of frames (Section 3): each group's tree holds the
+    colours of all its frames; the merge counts groups."""
+    rng = np.random.default_rng(seed)
+    for trial in range(5):
+        d = int(rng.integers(1, 7))
+        W, H = int(rng.integers(1, 11)), int(rng.integers(1, 7))
+        rw, rh = ((3, 2) if trial % 2 else (0, 0))
+        T = int(rng.integers(1, 9))
+        gsz = int(rng.integers(1, T + 1))
+        frames = brute.tiny_frames(rng, T + 2, W, H, n_colours=int(rng.integers(2, 8)), row_pitch=3 * W + 3)
+        train, test = frames[:T], frames[T:]
+        G = (T + gsz - 1) // gsz
+        k = int(rng.integers(1, G + 1))
+        f = O.Forest(W, H, d, rw, rh, mutant=mutant)
+        idx = [f.add_group(train[i: i + gsz]) for i in range(0, T, gsz)]
+        assert len(idx) == G
+        model = f.merge(idx, k, G)
+        kept = brute.grouped_sets(train, gsz, W, H, d, k, G, rw, rh)
+        leaf = model.leafset()
+        for r in range(leaf.shape[0]):
+            assert brute.bitset_triples(leaf[r], d) == kept[r], (trial, r)
+        for fr in test:
+            got, _ = brute.unpack_mask(model.classify(fr), W)
+            assert np.array_equal(got, brute.mask_bits(fr, kept, W, H, d, rw, rh)), trial
+    # one group of every frame at threshold 1: the union of the frames' colours
+    frames = brute.tiny_frames(rng, 4, 6, 5, n_colours=12)
+    f = O.Forest(6, 5, 3, mutant=mutant)
+    union = set().union(*[brute.frame_sets(fr, 6, 5, 3)[0] for fr in frames])
+    assert brute.bitset_triples(f.merge([f.add_group(frames)], 1, 1).leafset()[0], 3) == union
+
+
 def check_union_and_training_background(O, seed, mutant=0):
     """Threshold of one frame: every training pixel is background."""
     rng = np.random.default_rng(seed)
@@ -135,6 +167,11 @@ def test_brute_force_plain(oracle_lib, seed):
 @pytest.mark.parametrize("seed", range(3))
 def test_brute_force_regions(oracle_lib, seed):
     check_brute(oracle_lib, 100 + seed, regions=(3, 2))
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_brute_force_groups(oracle_lib, seed):
+    check_groups(oracle_lib, 300 + seed)
 
 
 def test_brute_force_direct_depth(oracle_lib):
@@ -311,6 +348,7 @@ MUTANTS = {
     7: "pruning removes one level too many",
     8: "mask polarity inverted",
     9: "numberOfTrees off by one in the merge test",
+    10: "a group's tree built from its first frame only",
 }
 
 
@@ -321,6 +359,7 @@ def _pin_battery(O, mutant):
         check_brute(O, 1000 + s, mutant)
     check_brute(O, 2000, mutant, regions=(3, 2))
     check_union_and_training_background(O, 3000, mutant)
+    check_groups(O, 4000, mutant)
 
 
 @pytest.mark.parametrize("mutant", sorted(MUTANTS))
