@@ -513,6 +513,19 @@ def main():
         if r:
             fused.append(e0.elapsed_time(e1))
     fused_ms = sum(fused) / len(fused)
+    # redraw of the test frames with their own pruned trees (Section 2)
+    qout = torch.empty_like(test)
+    qts = []
+    for r in range(min(a.steps, 10) + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        obg.obg_quantize(g, test, N, qout)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            qts.append(e0.elapsed_time(e1))
+    q_ms = sorted(qts)[len(qts) // 2]
+    del qout
     fused_same = bool(torch.equal(mask_f, mask))
     occ_bytes = N * g.n_regions * g.words * 4
 
@@ -552,6 +565,8 @@ def main():
         "train_merge_ms": round(ms_step - cls_avg, 4),
         "merge": {"ms_p50": round(merge_ms, 4), "groups_of_5_ms_p50": round(merge_g5_ms, 4),
                   "bitset_bytes_read": T * g.n_regions * g.words * 4},
+        "redraw": {"ms_p50": round(q_ms, 4), "gpixel_s": round(N * spec.pixels / (q_ms * 1e-3) / 1e9, 3),
+                   "tb_s": round(6 * N * spec.pixels / (q_ms * 1e-3) / 1e12, 3)},
         "classify_occ": {"ms_avg": round(fused_ms, 4),
                          "gpixel_s": round(N * spec.pixels / (fused_ms * 1e-3) / 1e9, 3),
                          "tb_s": round((cls_bytes + occ_bytes) / (fused_ms * 1e-3) / 1e12, 3),

@@ -143,6 +143,19 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
                  hipStream_t stream);
 
 /*
+ * Redraw (Section 2): every frame redrawn with its own pruned octree.  The
+ * colour of a depth-d node is its path bits with the remaining 8-d bits zero,
+ * and a frame's tree holds every pixel's node, so each channel keeps its top
+ * d bits: out byte = rgb byte & (0xFF << (8 - d)).
+ *   rgb, out : n_frames frames in the layout above (the same geometry),
+ *              16-byte aligned; out may be rgb itself (in place) but must not
+ *              otherwise overlap it.  Row padding of out is not written.
+ * Regions do not change the result (a pixel's colour is in its region's tree).
+ * n_frames = 0 enqueues nothing.
+ */
+int obg_quantize(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, uint8_t *out, hipStream_t stream);
+
+/*
  * Batched form: many independent streams of uneven resolution, depth,
  * training length and threshold.  obg_batch_run enqueues the whole batch as
  * three steps, each ONE persistent launch over all streams: the per-frame

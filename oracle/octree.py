@@ -44,6 +44,7 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
         "orc_forest_regions": (_I, [_P]),
         "orc_forest_add_frame": (_I, [_P, _P, _I64, _I]),
         "orc_forest_add_group": (_I, [_P, _P, _I, _I64, _I]),
+        "orc_redraw": (_I, [_P, _I, _P, _I64, _P, _I64]),
         "orc_forest_add_occupancy": (_I, [_P, _P]),
         "orc_forest_frame_export": (_I, [_P, _I, _P, _P]),
         "orc_forest_frame_nodes": (_I64, [_P, _I]),
@@ -148,6 +149,16 @@ class Forest:
 
     def drop(self, frame: int):
         self.lib.orc_forest_drop_frame(self.h, frame)
+
+    def redraw(self, frame: int, rgb: np.ndarray) -> np.ndarray:
+        """The frame (which built tree `frame`) redrawn with that tree's leaf
+        colours: [height, 3 * width] uint8."""
+        rgb = np.ascontiguousarray(rgb, dtype=np.uint8)
+        out = np.zeros((self.height, 3 * self.width), dtype=np.uint8)
+        rc = self.lib.orc_redraw(self.h, frame, _ptr(rgb), rgb.shape[1], _ptr(out), out.shape[1])
+        if rc != 0:
+            raise ValueError("oracle: a pixel's path is missing from the frame's tree")
+        return out
 
     def merge(self, frames: Sequence[int], num: int, den: int) -> "Model":
         idx = np.ascontiguousarray(frames, dtype=np.int32)

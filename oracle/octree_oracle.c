@@ -19,6 +19,8 @@
  *   - regions       : one tree per spatial region, Sections 3 and 4.
  *   - add_group     : one tree holding the colours of a group of frames
  *                     (Section 3 allows a tree per frame or per group).
+ *   - redraw        : a frame redrawn with its pruned trees' leaf colours
+ *                     (the zero-filled path bits, Section 2).
  *
  * Readings of points the paper leaves open (each one is listed with its
  * justification in the design notes of the repository):
@@ -567,6 +569,39 @@ int orc_classify(const Model *m, const uint8_t *rgb, int64_t row_pitch, uint64_t
             if (!check_color(root, p[0], p[1], p[2], g->depth))
 #endif
                 mrow[x >> 6] |= 1ull << (x & 63);
+        }
+    }
+    return 0;
+}
+
+/* Redraw a frame with its own pruned trees (Section 2): each pixel takes the
+ * colour of the depth-d node its path reaches, i.e. the node's path bits with
+ * the remaining bits zero.  The colour is rebuilt from the child indices met on
+ * the walk.  Returns -1 if some pixel's path is missing from its tree. */
+int orc_redraw(const Forest *f, int frame, const uint8_t *rgb, int64_t row_pitch, uint8_t *out,
+               int64_t out_pitch) {
+    const Geom *g = &f->g;
+    if (frame < 0 || frame >= f->nframes || !f->frames[frame]) return -1;
+    const Trees *t = f->frames[frame];
+    for (int y = 0; y < g->height; ++y) {
+        const uint8_t *row = rgb + (int64_t)y * row_pitch;
+        uint8_t *orow = out + (int64_t)y * out_pitch;
+        for (int x = 0; x < g->width; ++x) {
+            const uint8_t *p = row + 3 * x;
+            const Node *node = t->roots[region_of(g, x, y)];
+            if (!node) return -1;
+            unsigned R = 0, G = 0, B = 0;
+            for (int i = 0; i < g->depth; ++i) {
+                const int index = child_index(p[0], p[1], p[2], i);
+                if (!node->child[index]) return -1;
+                node = node->child[index];
+                R |= (unsigned)((index >> 2) & 1) << (7 - i);
+                G |= (unsigned)((index >> 1) & 1) << (7 - i);
+                B |= (unsigned)(index & 1) << (7 - i);
+            }
+            orow[3 * x] = (uint8_t)R;
+            orow[3 * x + 1] = (uint8_t)G;
+            orow[3 * x + 2] = (uint8_t)B;
         }
     }
     return 0;

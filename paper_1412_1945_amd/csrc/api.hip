@@ -342,6 +342,31 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, const 
     return run_pixels(o, mode, rgb, n_frames, leafset, mask, occ_out, nullptr, stream);
 }
 
+int obg_quantize(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, uint8_t *out, hipStream_t stream) {
+    Geo o;
+    int rc = check_geom(g, &o, true);
+    if (rc) return rc;
+    if (n_frames < 0) return fail(OBG_EINVAL, "n_frames < 0");
+    if (n_frames == 0) return OBG_OK;
+    if (!rgb || !out) return fail(OBG_EINVAL, "rgb and out must not be NULL");
+    if ((uintptr_t)rgb % 16 || (uintptr_t)out % 16) return fail(OBG_EALIGN, "rgb and out must be 16-byte aligned");
+    const uintptr_t a0 = (uintptr_t)rgb, a1 = a0 + (uintptr_t)n_frames * (uintptr_t)o.frame_pitch;
+    const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (uintptr_t)n_frames * (uintptr_t)o.frame_pitch;
+    if (a0 != b0 && a0 < b1 && b0 < a1) return fail(OBG_EINVAL, "rgb and out overlap without being the same buffer");
+    QuantArgs a{};
+    a.rgb = rgb;
+    a.out = out;
+    a.frame_pitch = o.frame_pitch;
+    a.row_pitch = o.row_pitch;
+    a.width = o.width;
+    a.height = o.height;
+    a.n_frames = n_frames;
+    a.depth = o.depth;
+    hipError_t e = launch_quantize(a, stream);
+    if (e != hipSuccess) return hip_fail(e, "quantize kernel launch");
+    return OBG_OK;
+}
+
 int obg_tune_set(int key, int value) {
     if (key < 0 || key >= OBG_TUNE_COUNT) return fail(OBG_EINVAL, "unknown tuning key %d", key);
     if (value < 0) return fail(OBG_EINVAL, "tuning value must be >= 0");

@@ -70,6 +70,16 @@ hipError_t launch_strip(int depth, int mode, const StripArgs &a, int grid, int b
                         bool region, size_t lds_bytes, hipStream_t stream);
 // LDS bytes one workgroup of the strip kernel needs (0 = order not possible)
 size_t strip_lds_bytes(int depth, int mode, int reg_cols, int lay);
+// Frames redrawn with their own pruned trees' leaf colours: every channel
+// keeps its top `depth` bits.  rgb and out share the geometry; in place is
+// allowed (each byte is read and written by the same lane).
+struct QuantArgs {
+    const uint8_t *rgb;
+    uint8_t *out;
+    int64_t frame_pitch, row_pitch;
+    int32_t width, height, n_frames, depth;
+};
+hipError_t launch_quantize(const QuantArgs &a, hipStream_t stream);
 hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);

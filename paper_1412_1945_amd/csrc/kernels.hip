@@ -19,6 +19,8 @@
 // merge_kernel  per 32 keys: bit-sliced counters of the window's bitsets and
 //               a bit-sliced compare against the frame-count threshold
 //               (Algorithm 2 in closed form).
+#include <algorithm>
+
 #include "strip_core.h"
 
 namespace obg {
@@ -105,6 +107,57 @@ strip_kernel(StripArgs a) {
                              a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * tiles) * KW,
                              tiles, tid, BLOCK);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Redraw (Section 2): a pixel's colour in its frame's pruned tree is its depth-d
+// node, whose colour is the node's path bits with the remaining bits zero; the
+// frame's own tree holds every pixel's node, so the redraw keeps the top
+// `depth` bits of every byte.  One lane per 16 pixels (48 bytes); blockIdx.y
+// walks the frames.
+__global__ __launch_bounds__(256) void quantize_kernel(QuantArgs a, uint32_t keep, int frame0) {
+    const int f = frame0 + (int)blockIdx.y;
+    if (f >= a.n_frames) return;
+    const int gpr = (a.width + 15) / 16;
+    const uint32_t groups = (uint32_t)a.height * (uint32_t)gpr;
+    const uint8_t *src = a.rgb + (int64_t)f * a.frame_pitch;
+    uint8_t *dst = a.out + (int64_t)f * a.frame_pitch;
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += gridDim.x * blockDim.x) {
+        const uint32_t y = g / (uint32_t)gpr;
+        const uint32_t gx = g - y * (uint32_t)gpr;
+        const int64_t off = (int64_t)y * a.row_pitch + 48 * (int64_t)gx;
+        const int nv = min(16, a.width - 16 * (int)gx);
+        if (nv == 16) {
+            const uint4 *s4 = reinterpret_cast<const uint4 *>(src + off);
+            uint4 *d4 = reinterpret_cast<uint4 *>(dst + off);
+            uint4 v0 = s4[0], v1 = s4[1], v2 = s4[2];
+            v0.x &= keep; v0.y &= keep; v0.z &= keep; v0.w &= keep;
+            v1.x &= keep; v1.y &= keep; v1.z &= keep; v1.w &= keep;
+            v2.x &= keep; v2.y &= keep; v2.z &= keep; v2.w &= keep;
+            d4[0] = v0;
+            d4[1] = v1;
+            d4[2] = v2;
+        } else {
+            // the row's last, partial group: only its pixels' bytes
+            for (int b = 0; b < 3 * nv; ++b) dst[off + b] = src[off + b] & (uint8_t)keep;
+        }
+    }
+}
+
+hipError_t launch_quantize(const QuantArgs &a, hipStream_t stream) {
+    if (!a.rgb || !a.out || a.depth < 1 || a.depth > 8 || a.width < 1 || a.height < 1 || a.n_frames < 0)
+        return hipErrorInvalidValue;
+    if (a.n_frames == 0) return hipSuccess;
+    const uint32_t byte = (0xFFu << (8 - a.depth)) & 0xFFu;
+    const uint32_t keep = byte * 0x01010101u;
+    const int64_t groups = (int64_t)a.height * ((a.width + 15) / 16);
+    if (groups > 0xFFFFFFFFLL) return hipErrorInvalidValue;
+    int gx = (int)std::min<int64_t>((groups + 255) / 256, 2048);
+    for (int f0 = 0; f0 < a.n_frames; f0 += 65535) {
+        const int nf = std::min(65535, a.n_frames - f0);
+        hipLaunchKernelGGL(quantize_kernel, dim3(gx, nf), dim3(256), 0, stream, a, keep, f0);
+    }
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

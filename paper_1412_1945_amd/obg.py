@@ -111,6 +111,7 @@ def load() -> ctypes.CDLL:
             "obg_train_frame": (ctypes.c_int, [G, P, I32, P, P, P]),
             "obg_merge": (ctypes.c_int, [G, P, I32, I32, I32, U32, U32, P, P]),
             "obg_merge_groups": (ctypes.c_int, [G, P, I32, I32, I32, I32, U32, U32, P, P]),
+            "obg_quantize": (ctypes.c_int, [G, P, I32, P, P]),
             "obg_classify": (ctypes.c_int, [G, P, I32, P, P, P, P]),
             "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
@@ -134,7 +135,7 @@ def load() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
-            "obg_merge", "obg_merge_groups", "obg_classify", "obg_tune_set", "obg_tune_get", "obg_probe",
+            "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_tune_set", "obg_tune_get", "obg_probe",
             "obg_batch_create", "obg_batch_run", "obg_batch_info_get", "obg_batch_destroy",
             "obg_serve_run", "obg_last_error", "obg_version"]
 
@@ -253,6 +254,12 @@ def obg_classify(g: FrameGeom, rgb: torch.Tensor, n_frames: int, leafset: torch.
         _need(occ_out, torch.int32, n_frames * g.n_regions * g.words, "occ_out")
     _check(load().obg_classify(ctypes.byref(g.c()), _ptr(rgb), n_frames, _ptr(leafset),
                                _ptr(mask), _ptr(occ_out), _stream(stream)))
+
+
+def obg_quantize(g: FrameGeom, rgb: torch.Tensor, n_frames: int, out: torch.Tensor, stream=None):
+    _frames_ok(g, rgb, n_frames)
+    _frames_ok(g, out, n_frames)
+    _check(load().obg_quantize(ctypes.byref(g.c()), _ptr(rgb), n_frames, _ptr(out), _stream(stream)))
 
 
 TUNE_KEYS = {"train_block": 0, "occ_blind": 1, "occ_wg_per_cu": 2,

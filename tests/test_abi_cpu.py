@@ -119,6 +119,17 @@ def test_merge_groups_rejects_bad_group(lib):
     assert L.obg_merge_groups(ctypes.byref(g), FAKE, 4, 0, 4, 2, 0, 2, FAKE, None) == -1
 
 
+def test_quantize_rejects_bad_buffers(lib):
+    L = _raw(lib)
+    g = _geom(lib)
+    assert L.obg_quantize(ctypes.byref(g), None, 1, FAKE, None) == -1
+    assert L.obg_quantize(ctypes.byref(g), FAKE, 1, None, None) == -1
+    assert L.obg_quantize(ctypes.byref(g), FAKE, 1, ctypes.c_void_p(0x100008), None) == -2
+    # overlapping but not identical
+    assert L.obg_quantize(ctypes.byref(g), FAKE, 2, ctypes.c_void_p(0x100000 + 1536), None) == -1
+    assert L.obg_quantize(ctypes.byref(g), None, 0, None, None) == 0
+
+
 def test_classify_rejects_null(lib):
     L = _raw(lib)
     g = _geom(lib)

@@ -195,6 +195,32 @@ def test_merge_groups_of_frames(env):
         assert np.array_equal(u64(mask[0]), model.classify(frames[T]))
 
 
+@pytest.mark.parametrize("d", range(1, 9))
+def test_redraw_against_oracle(env, d):
+    """Redraw with each frame's own pruned tree (Section 2), ragged widths and
+    regions, in place and out of place, against the oracle's tree walk."""
+    obg, O = env
+    rng = np.random.default_rng(60 + d)
+    for W, H, rw, rh in [(1, 1, 0, 0), (15, 3, 0, 0), (16, 2, 0, 0), (33, 17, 0, 0), (100, 9, 32, 4), (257, 5, 0, 0)]:
+        rp = ((3 * W + 15) // 16) * 16
+        frames = brute.tiny_frames(rng, 3, W, H, n_colours=(None if W % 2 else 9), row_pitch=rp)
+        g = obg.FrameGeom(W, H, d, region_w=rw, region_h=rh)
+        print(f"[case] redraw W={W} H={H} d={d} region={rw}x{rh}", flush=True)
+        dev = upload(frames, g.frame_pitch)
+        out = torch.full_like(dev, 0xA5)
+        obg.obg_quantize(g, dev, 3, out)
+        inplace = dev.clone()
+        obg.obg_quantize(g, inplace, 3, inplace)
+        torch.cuda.synchronize()
+        f = O.Forest(W, H, d, rw, rh)
+        for t in range(3):
+            want = f.redraw(f.add_frame(frames[t]), frames[t])
+            got = out[t].cpu().numpy().reshape(H, rp)
+            assert np.array_equal(got[:, : 3 * W], want), (W, H, t)
+            assert (got[:, 3 * W:] == 0xA5).all()          # row padding untouched
+            assert np.array_equal(inplace[t].cpu().numpy().reshape(H, rp)[:, : 3 * W], want)
+
+
 def test_fused_classify_occupancy(env):
     obg, O = env
     rng = np.random.default_rng(3)

@@ -135,6 +135,27 @@ def check_groups(O, seed, mutant=0):
     assert brute.bitset_triples(f.merge([f.add_group(frames)], 1, 1).leafset()[0], 3) == union
 
 
+def check_redraw(O, seed, mutant=0):
+    """Redraw with the frame's own pruned tree (Section 2): every pixel takes
+    its leaf's zero-filled colour, i.e. each channel keeps its top d bits; the
+    redrawn colours are exactly the tree's leaves."""
+    rng = np.random.default_rng(seed)
+    for trial in range(6):
+        d = int(rng.integers(1, 9))
+        W, H = int(rng.integers(1, 12)), int(rng.integers(1, 7))
+        rw, rh = ((4, 3) if trial % 3 == 2 else (0, 0))
+        fr = brute.tiny_frames(rng, 1, W, H, n_colours=(None if trial % 2 else 6), row_pitch=3 * W + 7)[0]
+        f = O.Forest(W, H, d, rw, rh, mutant=mutant)
+        i = f.add_frame(fr)
+        out = f.redraw(i, fr)
+        q = brute.quantised(fr, W, d)
+        assert np.array_equal(out.reshape(H, W, 3), (q << (8 - d)).astype(np.uint8)), trial
+        leaves = set().union(*[brute.bitset_triples(w, d) for w in f.export(i)])
+        assert {tuple(int(v) >> (8 - d) for v in px) for px in out.reshape(-1, 3)} == leaves, trial
+        if d == 8:
+            assert np.array_equal(out, fr[:, : 3 * W])
+
+
 def check_union_and_training_background(O, seed, mutant=0):
     """Threshold of one frame: every training pixel is background."""
     rng = np.random.default_rng(seed)
@@ -172,6 +193,11 @@ def test_brute_force_regions(oracle_lib, seed):
 @pytest.mark.parametrize("seed", range(3))
 def test_brute_force_groups(oracle_lib, seed):
     check_groups(oracle_lib, 300 + seed)
+
+
+@pytest.mark.parametrize("seed", range(2))
+def test_redraw_keeps_top_bits(oracle_lib, seed):
+    check_redraw(oracle_lib, 500 + seed)
 
 
 def test_brute_force_direct_depth(oracle_lib):
@@ -360,6 +386,7 @@ def _pin_battery(O, mutant):
     check_brute(O, 2000, mutant, regions=(3, 2))
     check_union_and_training_background(O, 3000, mutant)
     check_groups(O, 4000, mutant)
+    check_redraw(O, 5000, mutant)
 
 
 @pytest.mark.parametrize("mutant", sorted(MUTANTS))
