@@ -7,6 +7,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+#include <vector>
+
 namespace {
 
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
@@ -38,9 +41,9 @@ struct StreamConst {
 // b, R, G, B
 // The 16 pixels x0 = 16*gx .. x0+15 of row y of one frame (fewer at the row
 // end), written as 48 bytes with three 16-byte stores when the group is whole.
+template <typename NT>
 __device__ __forceinline__ void gen_group(const StreamConst &sc, const int32_t *__restrict__ r,
-                                          const int16_t *__restrict__ ntab, uint8_t *__restrict__ fo, int y,
-                                          int gx) {
+                                          const NT *__restrict__ ntab, uint8_t *__restrict__ fo, int y, int gx) {
     const int f = r[0];
     const uint32_t hf = (uint32_t)r[1];
     const int32_t scale = r[2];
@@ -151,11 +154,16 @@ struct IngestJob {
     StreamConst sc;
     const int32_t *rec;
     uint8_t *out;
+    int64_t g0;              // first 16-pixel group of this frame in the launch
 };
 
-// Frames of many streams: blockIdx.y = job.
-__global__ __launch_bounds__(256) void gen_batch_kernel(const IngestJob *__restrict__ jobs, int n_jobs,
-                                                        const int16_t *__restrict__ ntab) {
+constexpr int kGenBlock = 1024;
+constexpr int64_t kGenLdsMinGroups = 1 << 19;   // about 8 Mpx: below, the direct kernel is quicker
+
+// Frames of many streams, one job per blockIdx.y, noise looked up in HBM: for
+// small batches, where filling an LDS table would cost more than it saves.
+__global__ __launch_bounds__(256) void gen_jobs_kernel(const IngestJob *__restrict__ jobs, int n_jobs,
+                                                       const int16_t *__restrict__ ntab) {
     const int j = blockIdx.y;
     if (j >= n_jobs) return;
     const IngestJob &job = jobs[j];
@@ -165,6 +173,36 @@ __global__ __launch_bounds__(256) void gen_batch_kernel(const IngestJob *__restr
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < groups; g += gridDim.x * blockDim.x) {
         const int y = (int)(g / (uint32_t)ngx);
         gen_group(sc, job.rec, ntab, job.out, y, (int)(g - (uint32_t)y * ngx));
+    }
+}
+
+// Frames of many streams: their 16-pixel groups numbered end to end, equal
+// runs per workgroup.  The noise table (|values| <= 127) is copied to LDS as
+// bytes once per workgroup: its per-pixel lookups are scattered.
+__global__ __launch_bounds__(kGenBlock) __attribute__((amdgpu_waves_per_eu(8))) void gen_batch_kernel(const IngestJob *__restrict__ jobs, int n_jobs,
+                                                              int64_t n_groups, int64_t chunk,
+                                                              const int16_t *__restrict__ ntab) {
+    __shared__ int8_t nt[65536];
+    for (int i = threadIdx.x; i < 65536; i += kGenBlock) nt[i] = (int8_t)ntab[i];
+    __syncthreads();
+    const int64_t gb = (int64_t)blockIdx.x * chunk;
+    const int64_t ge = min(gb + chunk, n_groups);
+    int j = -1;
+    for (int64_t g = gb + threadIdx.x; g < ge; g += kGenBlock) {
+        if (j < 0) {
+            int lo = 0, hi = n_jobs - 1;      // last job whose first group is <= g
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (jobs[mid].g0 <= g) lo = mid; else hi = mid - 1;
+            }
+            j = lo;
+        }
+        while (j + 1 < n_jobs && jobs[j + 1].g0 <= g) ++j;
+        const IngestJob &job = jobs[j];
+        const int ngx = (job.sc.width + 15) / 16;
+        const uint32_t local = (uint32_t)(g - job.g0);
+        const int y = (int)(local / (uint32_t)ngx);
+        gen_group(job.sc, job.rec, nt, job.out, y, (int)(local - (uint32_t)y * ngx));
     }
 }
 
@@ -180,6 +218,7 @@ struct IngestCtx {
     hipEvent_t *slot_done;       // per slot: its last use has run on the device
     bool *slot_used;
     int slots, next_slot;
+    int cus;
 };
 
 constexpr int kMaxJobs = 4096;
@@ -224,6 +263,17 @@ extern "C" void *synth_ingest_create(int32_t n_streams, const int32_t *params, c
               hipMalloc((void **)&c->d_jobs, sizeof(IngestJob) * kMaxJobs * slots) == hipSuccess;
     for (int i = 0; ok && i < slots; ++i)
         ok = hipEventCreateWithFlags(&c->slot_done[i], hipEventDisableTiming) == hipSuccess;
+    // the batch kernel keeps the noise table in LDS as bytes
+    if (ok) {
+        std::vector<int16_t> h(65536);
+        ok = hipMemcpy(h.data(), d_ntab, 65536 * sizeof(int16_t), hipMemcpyDeviceToHost) == hipSuccess;
+        for (int i = 0; ok && i < 65536; ++i) ok = h[i] >= -127 && h[i] <= 127;
+    }
+    c->cus = 256;
+    int dev = 0, ncu = 0;
+    if (ok && hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        c->cus = ncu;
     if (!ok) {
         synth_ingest_destroy(c);
         return nullptr;
@@ -259,7 +309,7 @@ extern "C" int synth_ingest(void *ctx, const SynthIngestItem *items, int32_t n, 
     if (c->slot_used[slot] && hipEventSynchronize(c->slot_done[slot]) != hipSuccess) return -3;
     IngestJob *hj = c->h_jobs + (size_t)slot * kMaxJobs;
     IngestJob *dj = c->d_jobs + (size_t)slot * kMaxJobs;
-    int64_t maxpx = 0;
+    int64_t n_groups = 0;
     for (int i = 0; i < n; ++i) {
         const int s = items[i].stream, f = items[i].frame;
         if (s < 0 || s >= c->n_streams || f < 0 || f >= c->n_recs[s] || !items[i].dst ||
@@ -268,14 +318,26 @@ extern "C" int synth_ingest(void *ctx, const SynthIngestItem *items, int32_t n, 
         hj[i].sc = c->consts[s];
         hj[i].rec = c->d_recs + (c->rec_base[s] + f) * kFrameInts;
         hj[i].out = items[i].dst;
-        const int64_t px = (int64_t)hj[i].sc.width * hj[i].sc.height;
-        if (px > maxpx) maxpx = px;
+        hj[i].g0 = n_groups;
+        n_groups += (int64_t)hj[i].sc.height * ((hj[i].sc.width + 15) / 16);
     }
     if (hipMemcpyAsync(dj, hj, sizeof(IngestJob) * n, hipMemcpyHostToDevice, stream) != hipSuccess) return -3;
-    int gx = (int)((maxpx / 16 + 255) / 256);
-    if (gx > 1024) gx = 1024;
-    if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(gen_batch_kernel, dim3(gx, n), dim3(256), 0, stream, (const IngestJob *)dj, n, c->d_ntab);
+    if (n_groups < kGenLdsMinGroups) {
+        int64_t most = 0;
+        for (int i = 0; i < n; ++i) most = std::max<int64_t>(most, (int64_t)hj[i].sc.height * ((hj[i].sc.width + 15) / 16));
+        const int gx = (int)std::min<int64_t>((most + 255) / 256, 1024);
+        hipLaunchKernelGGL(gen_jobs_kernel, dim3(gx, n), dim3(256), 0, stream, (const IngestJob *)dj, n, c->d_ntab);
+        if (hipGetLastError() != hipSuccess || hipEventRecord(c->slot_done[slot], stream) != hipSuccess) return -3;
+        c->slot_used[slot] = true;
+        return 0;
+    }
+    // equal runs of groups, at least 8 per thread, at most two workgroups per CU
+    int64_t grid = std::min<int64_t>((n_groups + 8 * kGenBlock - 1) / (8 * kGenBlock), 2 * (int64_t)c->cus);
+    grid = std::max<int64_t>(grid, 1);
+    const int64_t chunk = (n_groups + grid - 1) / grid;
+    grid = (n_groups + chunk - 1) / chunk;
+    hipLaunchKernelGGL(gen_batch_kernel, dim3((unsigned)grid), dim3(kGenBlock), 0, stream, (const IngestJob *)dj, n,
+                       n_groups, chunk, c->d_ntab);
     if (hipGetLastError() != hipSuccess || hipEventRecord(c->slot_done[slot], stream) != hipSuccess) return -3;
     c->slot_used[slot] = true;
     return 0;
