@@ -440,10 +440,21 @@ def main():
         flat.fill_(7)
         print(json.dumps({"probe": run_probes(obg, torch, flat, nbytes), "bytes": nbytes}), flush=True)
         return
+    # ground truth of the test frames (the generator's foreground), packed in
+    # the mask layout, for Section 5's agreement figures
+    truth = torch.zeros((N, spec.height, g.mask_row_words), dtype=torch.int64, device=dev)
+    shifts = torch.arange(64, device=dev, dtype=torch.int64)
     chunk = 50
     for i in range(0, T + N, chunk):
         ids = list(range(i, min(T + N, i + chunk)))
-        make_frames(spec, ids, device=dev, out=frames[ids[0]: ids[-1] + 1])
+        _, tr = make_frames(spec, ids, device=dev, out=frames[ids[0]: ids[-1] + 1], with_truth=True)
+        lo = max(ids[0], T)
+        if lo <= ids[-1]:
+            tb = torch.zeros((len(ids), spec.height, g.mask_row_words * 64), dtype=torch.int64, device=dev)
+            tb[:, :, : spec.width] = tr.to(torch.int64)
+            packed = (tb.view(len(ids), spec.height, g.mask_row_words, 64) << shifts).sum(-1)
+            truth[lo - T: ids[-1] + 1 - T] = packed[lo - ids[0]:]
+        del tr
     torch.cuda.synchronize()
     train, test = frames[:T], frames[T:]
     occ = obg.empty_occ(g, T)
@@ -484,6 +495,19 @@ def main():
     torch.cuda.synchronize()
     cls_ms = sorted(e[0].elapsed_time(e[1]) for e in evs)
     cls_avg = sum(cls_ms) / len(cls_ms)
+
+    # agreement with the ground truth (Section 5's background-class figures)
+    counts = torch.zeros(3, dtype=torch.int64, device=dev)
+    obg.obg_score(g, mask, truth, N, counts)
+    tp, fp, fn = (int(v) for v in counts.cpu().tolist())
+    tn = N * spec.pixels - tp - fp - fn
+    p0 = tn / (tn + fn) if tn + fn else 0.0
+    r0 = tn / (tn + fp) if tn + fp else 0.0
+    accuracy = {"f0": round(2 * p0 * r0 / (p0 + r0), 6) if p0 + r0 else 0.0, "p0": round(p0, 6),
+                "r0": round(r0, 6), "foreground_recall": round(tp / (tp + fn), 4) if tp + fn else None,
+                "foreground_precision": round(tp / (tp + fp), 4) if tp + fp else None,
+                "truth": "synthetic foreground objects of the generator"}
+    del truth
 
     # the merge alone, and over trees of groups of 5 frames (Section 3)
     def time_merge(group, reps=20):
@@ -565,6 +589,7 @@ def main():
         "train_merge_ms": round(ms_step - cls_avg, 4),
         "merge": {"ms_p50": round(merge_ms, 4), "groups_of_5_ms_p50": round(merge_g5_ms, 4),
                   "bitset_bytes_read": T * g.n_regions * g.words * 4},
+        "accuracy": accuracy,
         "redraw": {"ms_p50": round(q_ms, 4), "gpixel_s": round(N * spec.pixels / (q_ms * 1e-3) / 1e9, 3),
                    "tb_s": round(6 * N * spec.pixels / (q_ms * 1e-3) / 1e12, 3)},
         "classify_occ": {"ms_avg": round(fused_ms, 4),

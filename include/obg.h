@@ -156,6 +156,20 @@ int obg_classify(const obg_geom *g, const uint8_t *rgb, int32_t n_frames,
 int obg_quantize(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, uint8_t *out, hipStream_t stream);
 
 /*
+ * Agreement of foreground masks with ground-truth masks, for the figures of
+ * Section 5 (F0 of the background class: P0 = Tn / (Tn + Fn), R0 = Tn /
+ * (Tn + Fp), F0 = 2 P0 R0 / (P0 + R0)).
+ *   mask, truth : [n_frames][height][ceil(width/64)] uint64 each, the mask
+ *                 layout (1 = foreground); bits past width are ignored.
+ *   counts      : out, device, 3 uint64: true positives, false positives,
+ *                 false negatives over all frames (overwritten).  True
+ *                 negatives = n_frames * width * height minus the three.
+ * Only width and height of g are used.  n_frames = 0 writes zeros.
+ */
+int obg_score(const obg_geom *g, const uint64_t *mask, const uint64_t *truth, int32_t n_frames, uint64_t *counts,
+              hipStream_t stream);
+
+/*
  * Batched form: many independent streams of uneven resolution, depth,
  * training length and threshold.  obg_batch_run enqueues the whole batch as
  * three steps, each ONE persistent launch over all streams: the per-frame

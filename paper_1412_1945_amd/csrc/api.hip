@@ -367,6 +367,24 @@ int obg_quantize(const obg_geom *g, const uint8_t *rgb, int32_t n_frames, uint8_
     return OBG_OK;
 }
 
+int obg_score(const obg_geom *g, const uint64_t *mask, const uint64_t *truth, int32_t n_frames, uint64_t *counts,
+              hipStream_t stream) {
+    Geo o;
+    int rc = check_geom(g, &o, false);
+    if (rc) return rc;
+    if (n_frames < 0) return fail(OBG_EINVAL, "n_frames < 0");
+    if (!counts) return fail(OBG_EINVAL, "counts must not be NULL");
+    if (n_frames > 0 && (!mask || !truth)) return fail(OBG_EINVAL, "mask and truth must not be NULL");
+    if ((uintptr_t)mask % 8 || (uintptr_t)truth % 8 || (uintptr_t)counts % 8)
+        return fail(OBG_EALIGN, "mask, truth and counts must be 8-byte aligned");
+    hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t *>(counts), 6, 0u, stream);
+    if (e == hipSuccess)
+        e = launch_score(mask, truth, (int64_t)n_frames * o.height, o.mask_row_words, o.width,
+                         reinterpret_cast<unsigned long long *>(counts), stream);
+    if (e != hipSuccess) return hip_fail(e, "score kernel launch");
+    return OBG_OK;
+}
+
 int obg_tune_set(int key, int value) {
     if (key < 0 || key >= OBG_TUNE_COUNT) return fail(OBG_EINVAL, "unknown tuning key %d", key);
     if (value < 0) return fail(OBG_EINVAL, "tuning value must be >= 0");

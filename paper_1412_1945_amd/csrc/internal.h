@@ -80,6 +80,10 @@ struct QuantArgs {
     int32_t width, height, n_frames, depth;
 };
 hipError_t launch_quantize(const QuantArgs &a, hipStream_t stream);
+// Agreement of masks with ground-truth masks (same layout): counts[0] true
+// positives, counts[1] false positives, counts[2] false negatives, added to.
+hipError_t launch_score(const uint64_t *mask, const uint64_t *truth, int64_t rows, int32_t row_words,
+                        int32_t width, unsigned long long *counts, hipStream_t stream);
 hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);

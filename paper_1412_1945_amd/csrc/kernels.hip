@@ -161,6 +161,46 @@ hipError_t launch_quantize(const QuantArgs &a, hipStream_t stream) {
 }
 
 // ---------------------------------------------------------------------------
+// Scoring against ground truth (Section 5's counts): popcounts of mask and
+// truth words, bits past the row's width ignored; per-wave sums, one atomic
+// add per wave and counter.
+__global__ __launch_bounds__(256) void score_kernel(const uint64_t *__restrict__ mask, const uint64_t *__restrict__ truth,
+                                                    int64_t n_words, int32_t row_words, int32_t width,
+                                                    unsigned long long *__restrict__ counts) {
+    const uint64_t last = (width & 63) ? ((1ull << (width & 63)) - 1ull) : ~0ull;
+    unsigned long long tp = 0, fp = 0, fn = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n_words;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const uint64_t valid = (i % row_words == row_words - 1) ? last : ~0ull;
+        const uint64_t m = mask[i] & valid, t = truth[i] & valid;
+        tp += __popcll(m & t);
+        fp += __popcll(m & ~t);
+        fn += __popcll(~m & t);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        tp += __shfl_xor(tp, off);
+        fp += __shfl_xor(fp, off);
+        fn += __shfl_xor(fn, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&counts[0], tp);
+        atomicAdd(&counts[1], fp);
+        atomicAdd(&counts[2], fn);
+    }
+}
+
+hipError_t launch_score(const uint64_t *mask, const uint64_t *truth, int64_t rows, int32_t row_words,
+                        int32_t width, unsigned long long *counts, hipStream_t stream) {
+    if (!mask || !truth || !counts || rows < 0 || row_words < 1 || width < 1 || width > 64 * row_words)
+        return hipErrorInvalidValue;
+    const int64_t n_words = rows * row_words;
+    if (n_words == 0) return hipSuccess;
+    const int grid = (int)std::min<int64_t>((n_words + 255) / 256, 4096);
+    hipLaunchKernelGGL(score_kernel, dim3(grid), dim3(256), 0, stream, mask, truth, n_words, row_words, width, counts);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Generic per-pixel kernel: one thread per 64-pixel mask word.
 
 __global__ __launch_bounds__(256) void generic_kernel(GenericArgs a, int mode) {

@@ -112,6 +112,7 @@ def load() -> ctypes.CDLL:
             "obg_merge": (ctypes.c_int, [G, P, I32, I32, I32, U32, U32, P, P]),
             "obg_merge_groups": (ctypes.c_int, [G, P, I32, I32, I32, I32, U32, U32, P, P]),
             "obg_quantize": (ctypes.c_int, [G, P, I32, P, P]),
+            "obg_score": (ctypes.c_int, [G, P, P, I32, P, P]),
             "obg_classify": (ctypes.c_int, [G, P, I32, P, P, P, P]),
             "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
@@ -135,7 +136,7 @@ def load() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
-            "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_tune_set", "obg_tune_get", "obg_probe",
+            "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_score", "obg_tune_set", "obg_tune_get", "obg_probe",
             "obg_batch_create", "obg_batch_run", "obg_batch_info_get", "obg_batch_destroy",
             "obg_serve_run", "obg_last_error", "obg_version"]
 
@@ -260,6 +261,15 @@ def obg_quantize(g: FrameGeom, rgb: torch.Tensor, n_frames: int, out: torch.Tens
     _frames_ok(g, rgb, n_frames)
     _frames_ok(g, out, n_frames)
     _check(load().obg_quantize(ctypes.byref(g.c()), _ptr(rgb), n_frames, _ptr(out), _stream(stream)))
+
+
+def obg_score(g: FrameGeom, mask: torch.Tensor, truth: torch.Tensor, n_frames: int, counts: torch.Tensor,
+              stream=None):
+    """counts: int64 GPU tensor of 3 (true positives, false positives, false negatives)."""
+    _need(mask, torch.int64, n_frames * g.height * g.mask_row_words, "mask")
+    _need(truth, torch.int64, n_frames * g.height * g.mask_row_words, "truth")
+    _need(counts, torch.int64, 3, "counts")
+    _check(load().obg_score(ctypes.byref(g.c()), _ptr(mask), _ptr(truth), n_frames, _ptr(counts), _stream(stream)))
 
 
 TUNE_KEYS = {"train_block": 0, "occ_blind": 1, "occ_wg_per_cu": 2,

@@ -130,6 +130,15 @@ def test_quantize_rejects_bad_buffers(lib):
     assert L.obg_quantize(ctypes.byref(g), None, 0, None, None) == 0
 
 
+def test_score_rejects_bad_buffers(lib):
+    L = _raw(lib)
+    g = _geom(lib)
+    assert L.obg_score(ctypes.byref(g), FAKE, FAKE, 1, None, None) == -1
+    assert L.obg_score(ctypes.byref(g), None, FAKE, 1, FAKE, None) == -1
+    assert L.obg_score(ctypes.byref(g), FAKE, ctypes.c_void_p(0x100004), 1, FAKE, None) == -2
+    assert L.obg_score(ctypes.byref(g), FAKE, FAKE, -1, FAKE, None) == -1
+
+
 def test_classify_rejects_null(lib):
     L = _raw(lib)
     g = _geom(lib)

@@ -221,6 +221,34 @@ def test_redraw_against_oracle(env, d):
             assert np.array_equal(inplace[t].cpu().numpy().reshape(H, rp)[:, : 3 * W], want)
 
 
+def test_score_against_plain_counts(env):
+    """Section 5's counts from masks and ground truth (bits past the width,
+    set at random in both, are ignored) against counting pixel by pixel."""
+    obg, O = env
+    from oracle import metrics as M
+    rng = np.random.default_rng(17)
+    for W, H, n in [(1, 1, 1), (63, 5, 3), (64, 4, 2), (65, 7, 2), (200, 9, 4), (1000, 3, 1)]:
+        g = obg.FrameGeom(W, H, 4)
+        mw = g.mask_row_words
+        m = rng.random((n, H, W)) < 0.3
+        t = rng.random((n, H, W)) < 0.2
+        def pack(b):
+            words = np.zeros((n, H, mw), dtype=np.uint64)
+            for x in range(W):
+                words[:, :, x >> 6] |= b[:, :, x].astype(np.uint64) << np.uint64(x & 63)
+            pad = rng.integers(0, 2 ** 63, (n, H), dtype=np.int64).astype(np.uint64) << np.uint64(1)
+            if W & 63:
+                words[:, :, -1] |= pad & ~np.uint64((1 << (W & 63)) - 1)
+            return torch.from_numpy(words.view(np.int64)).cuda()
+        print(f"[case] score W={W} H={H} n={n}", flush=True)
+        counts = torch.full((3,), -1, dtype=torch.int64, device="cuda")
+        obg.obg_score(g, pack(m), pack(t), n, counts)
+        torch.cuda.synchronize()
+        tp, fp, fn, tn = M.confusion(m, t)
+        assert counts.cpu().tolist() == [tp, fp, fn]
+        assert tn == n * W * H - tp - fp - fn
+
+
 def test_fused_classify_occupancy(env):
     obg, O = env
     rng = np.random.default_rng(3)
