@@ -321,8 +321,11 @@ int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
  * gives the same bytes.
  *   OBG_TUNE_TRAIN_BLOCK        threads per workgroup of occupancy-only
  *                               passes: 256 or 1024 (default 1024)
- *   OBG_TUNE_OCC_BLIND          reserved (occupancy bits are set with an
- *                               unconditional LDS atomic OR)
+ *   OBG_TUNE_OCC_BLIND          1 = set occupancy bits with an unconditional
+ *                               LDS atomic OR (default with regions and at
+ *                               d = 6), 2 = read the word first and OR only a
+ *                               clear bit (default otherwise: fewer colliding
+ *                               atomics when many pixels share a key)
  *   OBG_TUNE_OCC_WG_PER_CU      workgroups per CU of passes that build
  *                               occupancy (default 2 at 1024 threads, else 4)
  *   OBG_TUNE_CLASSIFY_WG_PER_CU workgroups per CU of classify-only passes

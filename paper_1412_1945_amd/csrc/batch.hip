@@ -448,6 +448,7 @@ int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t
         a.n_regions = 1;
         a.div_gpr = make_fastdiv((uint32_t)a.gpr);
         a.div_tile = make_fastdiv((uint32_t)a.gpr);
+        a.occ_test = tune(OBG_TUNE_OCC_BLIND, g.depth <= 5 ? 2 : 1) == 2;
         a.mask_row_words = (g.width + 63) / 64;
         if ((int64_t)g.height * a.gpr > (1LL << 30)) { destroy(b); return bfail(OBG_EINVAL, "stream %d: frame too large", s); }
         h.groups = g.height * a.gpr;

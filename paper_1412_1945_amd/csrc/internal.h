@@ -27,6 +27,7 @@ struct StripArgs {
     int32_t n_items;          // n_strips * n_frames * spans
     int32_t interleave;       // 1: item i goes to workgroup i % grid; 0: contiguous ranges
     int32_t stage_mask;       // 1: masks gathered in LDS per item (span <= 1024 groups)
+    int32_t occ_test;         // 1: read an occupancy word first, atomic OR only when the bit is clear
     const uint32_t *leaf;     // [n_regions][words], key order
     uint64_t *mask;           // [n_frames][height][mask_row_words]
     int32_t mask_row_words;
@@ -63,6 +64,8 @@ enum StripMode { MODE_MASK = 1, MODE_OCC = 2, MODE_COUNTS = 4 };
 
 // Record the calling thread's last error (read by obg_last_error); returns code.
 int set_error(int code, const char *msg);
+// Current value of launch knob `key` (obg_tune_set), or dflt when unset.
+int tune(int key, int dflt);
 
 // lay: LDS order (LAY_WIDE / LAY_COMPACT, see device.h); region: more than
 // one region per strip

@@ -95,7 +95,7 @@ __device__ __forceinline__ void fetch_group(__amdgpu_buffer_rsrc_t rs, const Str
 template <int D, int MODE, int PAD, bool GUARD>
 __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nvalid,
                                                  const uint32_t *leaf_tile, uint32_t *occ_tile,
-                                                 uint32_t *__restrict__ cnt) {
+                                                 uint32_t *__restrict__ cnt, bool occ_test) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
@@ -112,8 +112,10 @@ __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nv
             present |= ((w >> (bit & 31)) & 1u) << p;
         }
         if ((OCC || CNT) && (!GUARD || p < nvalid)) {
-            if (OCC) atomicOr(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(occ_tile) + addr),
-                              1u << (bit & 31));
+            if (OCC) {
+                uint32_t *w = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(occ_tile) + addr);
+                if (!occ_test || !((*w >> (bit & 31)) & 1u)) atomicOr(w, 1u << (bit & 31));
+            }
             if (CNT) {
                 const uint32_t l = (addr << 3) | (bit & 31);
                 if (l == run_l) {
@@ -151,9 +153,9 @@ __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffe
     uint32_t *cnt = CNT ? cbase + (int64_t)c * LC : nullptr;
     uint32_t present;
     if (nv == 16)
-        present = group_pixels<D, MODE, PAD, false>(u, 16, leaf_tile, occ_tile, cnt);
+        present = group_pixels<D, MODE, PAD, false>(u, 16, leaf_tile, occ_tile, cnt, a.occ_test != 0);
     else
-        present = group_pixels<D, MODE, PAD, true>(u, nv, leaf_tile, occ_tile, cnt);
+        present = group_pixels<D, MODE, PAD, true>(u, nv, leaf_tile, occ_tile, cnt, a.occ_test != 0);
     if (MASK) {
         // Four consecutive lanes hold the four 16-pixel groups of one 64-pixel
         // mask word (work spans and rows are multiples of 4 groups): gather

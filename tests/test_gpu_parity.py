@@ -312,6 +312,8 @@ KNOBS = [
     {"classify_span": 100, "mask_stage": 1},
     {"train_block": 256, "occ_wg_per_cu": 8},
     {"occ_wg_per_cu": 1},
+    {"occ_blind": 1},
+    {"occ_blind": 2},
 ]
 
 
