@@ -2,6 +2,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 
@@ -124,6 +125,8 @@ size_t strip_lds_max() {
 
 // Does the LDS strip kernel handle this geometry and mode?  Picks the LDS
 // order: the wide one when it fits, else the compact one.
+constexpr int64_t kOccItemsPerWg = 4;
+
 bool strip_ok(const Geo &g, int mode, int *lay) {
     if (g.depth > 6) return false;
     if (g.region_w && (g.region_w % 16) != 0) return false;
@@ -213,10 +216,22 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         int want = tune(OBG_TUNE_OCC_WG_PER_CU, block == 1024 ? 2 : 4);
         if (want > per_cu) want = per_cu;
         target = (int64_t)cus * want;
-        spans = (target + n_sf - 1) / n_sf;
-        const int64_t cap = (groups_strip + block - 1) / block;
-        if (spans > cap) spans = cap;
-        if (spans < 1) spans = 1;
+        // items per (frame, strip): workgroups take contiguous runs of items,
+        // so with n items the busiest one reads ceil(n / target) of them; pick
+        // the split whose busiest workgroup reads the least, and among nearly
+        // equal ones the fewest items (each segment change costs a flush)
+        const int64_t cap = std::max<int64_t>(1, (groups_strip + block - 1) / block);
+        const int64_t s0 = std::min<int64_t>(cap, std::max<int64_t>(1, (target + n_sf - 1) / n_sf));
+        spans = s0;
+        double best = 1e300;
+        for (int64_t sp = s0; sp <= std::min<int64_t>(cap, s0 * kOccItemsPerWg); ++sp) {
+            const int64_t n = n_sf * sp;
+            const double busiest = (double)((n + target - 1) / target) / (double)sp;   // in segments
+            if (busiest < best * 0.98) {
+                best = busiest;
+                spans = sp;
+            }
+        }
     } else {
         // measured on the 1080p stream: two 512-thread groups per CU streaming
         // 512-group items round-robin give the highest read+write rate
