@@ -39,6 +39,8 @@ def parse():
     p.add_argument("--serve-capacity-seconds", type=float, default=10.0,
                    help="seconds of arrivals offered all at once to measure the served capacity")
     p.add_argument("--serve-budget-gib", type=float, default=32.0)
+    p.add_argument("--serve-regions", type=int, default=0,
+                   help="serve this many 3840x2160 streams with 32x32 regions (d=4, T=30) instead of the mix")
     p.add_argument("--serve-inflight", type=int, default=3,
                    help="batches on the device at once in the real-time served run")
     p.add_argument("--serve-capacity-inflight", type=int, default=1,
@@ -259,7 +261,7 @@ def run_batched(a):
     print(json.dumps(out), flush=True)
 
 
-def oracle_served_replay(spec, depth, T, num, den, n_frames, period, window, budget_s):
+def oracle_served_replay(spec, depth, T, num, den, n_frames, period, window, budget_s, region=(0, 0)):
     """The oracle on one served stream: model from frames 0..T-1, then each
     test frame is classified and kept as a tree; every `period` test frames the
     model is re-merged from the trees of the last `window` frames.  Stops
@@ -267,7 +269,7 @@ def oracle_served_replay(spec, depth, T, num, den, n_frames, period, window, bud
     from oracle import octree
     from synth.frames import make_frames
     t0 = time.perf_counter()
-    f = octree.Forest(spec.width, spec.height, depth)
+    f = octree.Forest(spec.width, spec.height, depth, region[0], region[1])
     train = make_frames(spec, range(T), device="cpu").numpy()
     model = f.merge(f.add_frames(list(train)), num, den)
     trees, masks = {}, []
@@ -297,13 +299,23 @@ def run_served(a):
     from synth import frames as S
     from synth.fast import IngestContext, poisson_arrivals
     obg.load()
-    specs, depths, thrs, rates = S.cfg4()
+    if a.serve_regions:
+        import random as _random
+        rng = _random.Random("rates/regions")
+        specs = [S.StreamSpec(3840, 2160, 30, 0, seed=5, stream=i, bimodal_frac=0.2, drift_amp=0.1,
+                              fg="ellipses", fg_coverage=0.10) for i in range(a.serve_regions)]
+        depths, thrs = [4] * len(specs), [(1, 2)] * len(specs)
+        rates = [rng.uniform(5.0, 30.0) for _ in specs]
+        region = (32, 32)
+    else:
+        specs, depths, thrs, rates = S.cfg4()
+        region = (0, 0)
     period, window = 100, 50
     horizon = max(a.serve_seconds, a.serve_capacity_seconds)
     arrivals_all = poisson_arrivals(rates, horizon, seed=4)
     arrivals = [x[x < a.serve_seconds] for x in arrivals_all]
-    streams = [{"width": sp.width, "height": sp.height, "depth": d, "n_train": sp.n_train, "thr": thr}
-               for sp, d, thr in zip(specs, depths, thrs)]
+    streams = [{"width": sp.width, "height": sp.height, "depth": d, "n_train": sp.n_train, "thr": thr,
+                "region_w": region[0], "region_h": region[1]} for sp, d, thr in zip(specs, depths, thrs)]
     n_frames = [len(x) for x in arrivals]
     n_source = [len(x) for x in arrivals_all]
     # watched stream: the first smallest one, its masks kept for the oracle sample
@@ -343,7 +355,8 @@ def run_served(a):
         b = 0
         for sp, d, x in zip(specs, depths, arr):
             n, T = len(x), sp.n_train
-            words_b = max(4, (1 << (3 * d)) // 8)
+            n_reg = (-(-sp.width // region[0]) * -(-sp.height // region[1])) if region[0] else 1
+            words_b = max(4, (1 << (3 * d)) // 8) * n_reg
             px = sp.width * sp.height
             n_test = max(n - T, 0)
             b += n * (3 * px + words_b) + n_test * (sp.height * ((sp.width + 63) // 64) * 8 + words_b)
@@ -363,7 +376,8 @@ def run_served(a):
         "ms_per_step": round(cap["wall_s"] * 1e3, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u8", "data": "synthetic",
-        "config": {"workload": f"served-{len(specs)}-streams-mixed", "streams": len(specs),
+        "config": {"workload": (f"served-{len(specs)}-streams-3840x2160-regions32-d4" if region[0]
+                                else f"served-{len(specs)}-streams-mixed"), "streams": len(specs),
                    "fps_range": [5, 30], "offered_gpixel_s": round(sum(r * sp.width * sp.height for r, sp in
                                                                        zip(rates, specs)) / 1e9, 3),
                    "budget_gib": a.serve_budget_gib, "remerge_period": period, "remerge_window": window,
@@ -389,16 +403,18 @@ def run_served(a):
         "capacity_vs_realtime_identical": bool(same),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "served path in the capacity run: serve_kernel (occupancy of training "
-                               "frames, fused classify+occupancy of test frames) and the merges, timed with "
-                               "HIP events on the batch streams",
+                     "kernel": ("served path in the capacity run: the region passes (trees of training "
+                                "frames, classify + trees of test frames) and the merges" if region[0] else
+                                "served path in the capacity run: serve_kernel (occupancy of training "
+                                "frames, fused classify+occupancy of test frames) and the merges") +
+                               ", timed with HIP events on the batch streams",
                      "bytes": cap_bytes},
     }
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle replay of the watched stream)", file=sys.stderr, flush=True)
         sp = specs[small]
         got, dt = oracle_served_replay(sp, depths[small], sp.n_train, *thrs[small], n_frames[small],
-                                       period, window, budget_s=15.0)
+                                       period, window, budget_s=15.0, region=region)
         ok = bool(wmasks) and all(np.array_equal(wmasks[0][i], got[i]) for i in range(len(got)))
         px = (sp.n_train + len(got)) * sp.width * sp.height
         out["cpu_baseline"] = {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",

@@ -252,8 +252,11 @@ void obg_batch_destroy(obg_batch *batch);
  * (a 64-bit hash of the mask words, `checksums[s * checksum_stride + f]`,
  * NULL = off) and the full masks of the test frames of `watch_streams` copied
  * to host buffers (watch_masks[w], [watch_max_frames][height][ceil(width/64)]).
- * Streams: plain geometry, depth 1..6; pixels are packed RGB8 with row pitch
- * 3*width rounded up to 16 bytes.
+ * Streams: depth 1..6, one tree per frame or per region (Sections 3 and 4);
+ * pixels are packed RGB8 with row pitch 3*width rounded up to 16 bytes.
+ * Frames of streams without regions go through one launch per batch; frames
+ * of streams with regions take the one-stream passes (obg_train_frame,
+ * obg_classify with occ_out, obg_merge) on the batch's HIP stream.
  * Admission: a frame takes one arena block (its pixels, and for a test frame
  * its mask).  When a frame does not fit, its stream goes first and no other
  * frame is admitted until it does, so no stream starves; a frame that cannot
@@ -277,6 +280,7 @@ typedef struct obg_serve_stream {
     int32_t width, height, depth;
     int32_t n_train;
     uint32_t thr_num, thr_den;
+    int32_t region_w, region_h;   /* 0, 0 = one tree per frame; else regions as above */
 } obg_serve_stream;
 
 typedef struct obg_serve_config {

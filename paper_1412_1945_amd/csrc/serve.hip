@@ -174,6 +174,9 @@ struct StreamDev {
     obg_serve_stream cfg{};
     StripArgs a{};
     int words = 0, valid_bits = 32, groups = 0;
+    int n_regions = 1;
+    bool region = false;      // one tree per region: the one-stream passes serve it
+    obg_geom geom{};          // for those passes
 };
 
 struct Slot {
@@ -182,6 +185,8 @@ struct Slot {
     bool busy = false;
     SchedBatch batch;
     std::vector<double> arrival;   // per frame of the batch: wall seconds after the start
+    std::vector<int> order;        // launch order of the batch's frames (indices into batch.frames)
+    int n_train_plain = 0;         // order: plain training, plain test, region test, region training
     ServeFrameDev *h_frames = nullptr, *d_frames = nullptr;
     MergeJobDev *h_jobs = nullptr, *d_jobs = nullptr;
     obg_ingest_item *items = nullptr;
@@ -249,8 +254,19 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         if (c.width < 1 || c.height < 1 || c.depth < 1 || c.depth > 6 || c.n_train < 1 || c.n_train > 65535 ||
             c.thr_num == 0 || c.thr_den == 0 || cfg->n_arrivals[s] < 0 || (cfg->n_arrivals[s] && !cfg->arrivals[s]))
             return sfail(OBG_EINVAL, "bad stream description");
+        if (c.region_w < 0 || c.region_h < 0 || (c.region_w == 0) != (c.region_h == 0))
+            return sfail(OBG_EINVAL, "region_w and region_h must both be 0 or both be >= 1");
         StreamDev &sd = D[s];
         sd.cfg = c;
+        sd.region = c.region_w > 0;
+        sd.n_regions = sd.region ? ((c.width + c.region_w - 1) / c.region_w) * ((c.height + c.region_h - 1) / c.region_h) : 1;
+        sd.geom.width = c.width;
+        sd.geom.height = c.height;
+        sd.geom.row_pitch = ((3 * (int64_t)c.width + 15) / 16) * 16;
+        sd.geom.frame_pitch = sd.geom.row_pitch * c.height;
+        sd.geom.depth = c.depth;
+        sd.geom.region_w = c.region_w;
+        sd.geom.region_h = c.region_h;
         StripArgs &a = sd.a;
         a.width = c.width;
         a.height = c.height;
@@ -269,8 +285,9 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         sd.groups = c.height * a.gpr;
         sd.words = leaf_words(c.depth);
         sd.valid_bits = leaf_count(c.depth) < 32 ? leaf_count(c.depth) : 32;
-        sc[s] = {c.width, c.height, c.depth, c.n_train};
-        if (sched_frame_bytes(sc[s]) != (uint64_t)a.frame_pitch || sched_tree_bytes(sc[s]) != (uint64_t)sd.words * 4)
+        sc[s] = {c.width, c.height, c.depth, c.n_train, sd.n_regions};
+        if (sched_frame_bytes(sc[s]) != (uint64_t)a.frame_pitch ||
+            sched_tree_bytes(sc[s]) != (uint64_t)sd.words * 4 * (uint64_t)sd.n_regions)
             return sfail(OBG_EINVAL, "internal size mismatch");
     }
 
@@ -354,15 +371,15 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             busy_iv.push_back({ms_s, ms});
             path_iv.push_back({ms_k0, ms_k1});
             const double done_s = ms * 1e-3;
-            int ti = 0;
-            for (size_t i = 0; i < sl.batch.frames.size(); ++i) {
-                const SchedFrame &fr = sl.batch.frames[i];
+            for (size_t p = 0; p < sl.order.size(); ++p) {
+                const SchedFrame &fr = sl.batch.frames[sl.order[p]];
                 const int64_t px = (int64_t)D[fr.stream].cfg.width * D[fr.stream].cfg.height;
                 if (fr.test) {
-                    lat.push_back((done_s - sl.arrival[i]) * 1e3);
+                    lat.push_back((done_s - sl.arrival[p]) * 1e3);
+                    // test frames follow the plain training frames in launch order
                     if (cfg->checksums && fr.frame < cfg->checksum_stride)
-                        cfg->checksums[(int64_t)fr.stream * cfg->checksum_stride + fr.frame] = sl.h_sum[ti];
-                    ++ti;
+                        cfg->checksums[(int64_t)fr.stream * cfg->checksum_stride + fr.frame] =
+                            sl.h_sum[p - sl.n_train_plain];
                     ++test_frames;
                     test_pixels += px;
                 } else {
@@ -390,39 +407,55 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             Slot &sl = *free_slot;
             const std::vector<SchedFrame> &F = sl.batch.frames;
             const int n = (int)F.size();
-            int nt = 0;
-            while (nt < n && !F[nt].test) ++nt;
-            // descriptors, groups numbered end to end over the batch
+            // launch order: plain training, plain test, region test, region
+            // training frames; test frames are contiguous for the checksums
+            sl.order.clear();
+            for (int pass = 0; pass < 4; ++pass)
+                for (int i = 0; i < n; ++i) {
+                    const bool region = D[F[i].stream].region, test = F[i].test;
+                    if ((pass == 0 && !region && !test) || (pass == 1 && !region && test) ||
+                        (pass == 2 && region && test) || (pass == 3 && region && !test))
+                        sl.order.push_back(i);
+                }
+            int n_plain = 0, nt = 0, n_test_end = 0;
+            for (int p = 0; p < n; ++p) {
+                const SchedFrame &fr = F[sl.order[p]];
+                if (!D[fr.stream].region) ++n_plain;
+                if (!D[fr.stream].region && !fr.test) ++nt;
+                if (fr.test) n_test_end = p + 1;
+            }
+            sl.n_train_plain = nt;
+            // descriptors; the plain frames' groups are numbered end to end
             int64_t n_groups = 0;
             sl.arrival.resize(n);
-            for (int i = 0; i < n; ++i) {
-                const SchedFrame &fr = F[i];
+            for (int p = 0; p < n; ++p) {
+                const SchedFrame &fr = F[sl.order[p]];
                 const StreamDev &sd = D[fr.stream];
                 uint32_t *ring = reinterpret_cast<uint32_t *>(sched.S[fr.stream].ring);
-                ServeFrameDev &fd = sl.h_frames[i];
+                ServeFrameDev &fd = sl.h_frames[p];
                 fd.a = sd.a;
                 fd.rgb = fr.rgb;
-                fd.occ = ring + (int64_t)fr.slot * sd.words;
+                fd.occ = ring + (int64_t)fr.slot * sd.words * sd.n_regions;
                 fd.leaf = reinterpret_cast<uint32_t *>(sched.S[fr.stream].leaf);
                 fd.mask = fr.mask;
                 fd.depth = sd.cfg.depth;
-                fd.groups = sd.groups;
+                fd.groups = sd.region ? 0 : sd.groups;
                 fd.words = sd.words;
                 fd.pad_ = 0;
                 fd.g0 = n_groups;
-                n_groups += sd.groups;
-                sl.arrival[i] = cfg->arrivals[fr.stream][fr.frame] / cfg->speed;
-                sl.items[i].stream = fr.stream;
-                sl.items[i].frame = fr.frame;
-                sl.items[i].dst = fr.rgb;
+                n_groups += fd.groups;
+                sl.arrival[p] = cfg->arrivals[fr.stream][fr.frame] / cfg->speed;
+                sl.items[p].stream = fr.stream;
+                sl.items[p].frame = fr.frame;
+                sl.items[p].dst = fr.rgb;
             }
-            const int n_jobs = (int)sl.batch.merges.size();
-            for (int i = 0; i < n_jobs; ++i) {
-                const SchedMerge &m = sl.batch.merges[i];
-                merge_job(sl.h_jobs[i], D[m.stream], reinterpret_cast<const uint32_t *>(sched.S[m.stream].ring),
-                          reinterpret_cast<uint32_t *>(sched.S[m.stream].leaf), sched.S[m.stream].ring_len, m.first,
-                          m.n);
-            }
+            // merges of plain streams in one launch; region streams merge alone
+            int n_jobs = 0;
+            for (const SchedMerge &m : sl.batch.merges)
+                if (!D[m.stream].region)
+                    merge_job(sl.h_jobs[n_jobs++], D[m.stream], reinterpret_cast<const uint32_t *>(sched.S[m.stream].ring),
+                              reinterpret_cast<uint32_t *>(sched.S[m.stream].leaf), sched.S[m.stream].ring_len, m.first,
+                              m.n);
             hipStream_t st = sl.st;
             bool ok = hipEventRecord(sl.start, st) == hipSuccess;
             if (ok) ok = hipMemcpyAsync(sl.d_frames, sl.h_frames, sizeof(ServeFrameDev) * n, hipMemcpyHostToDevice, st) == hipSuccess;
@@ -431,25 +464,45 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             if (ok) ok = cfg->ingest(cfg->ingest_ctx, sl.items, n, st) == 0;
             if (ok) ok = hipEventRecord(sl.k0, st) == hipSuccess;
             if (ok) {
-                hipLaunchKernelGGL(serve_zero_kernel, dim3(8, n), dim3(256), 0, st, (const ServeFrameDev *)sl.d_frames);
-                // equal runs of groups, at least kMinChunk per workgroup so that
-                // a small batch does not pay for idle workgroups
-                const int64_t kMinChunk = 2048;
-                int64_t grid = std::min<int64_t>((n_groups + kMinChunk - 1) / kMinChunk, (int64_t)cus * 2);
-                grid = std::max<int64_t>(grid, 1);
-                const int64_t chunk = (((n_groups + grid - 1) / grid) + 3) & ~int64_t(3);
-                grid = (n_groups + chunk - 1) / chunk;
-                ServeArgs b{sl.d_frames, n, n_groups, chunk};
-                hipLaunchKernelGGL(serve_kernel, dim3((unsigned)grid), dim3(kServeBlock), 0, st, b);
-                if (n_jobs) {
+                if (n_plain) {
+                    hipLaunchKernelGGL(serve_zero_kernel, dim3(8, n_plain), dim3(256), 0, st,
+                                       (const ServeFrameDev *)sl.d_frames);
+                    // equal runs of groups, at least kMinChunk per workgroup so
+                    // that a small batch does not pay for idle workgroups
+                    const int64_t kMinChunk = 2048;
+                    int64_t grid = std::min<int64_t>((n_groups + kMinChunk - 1) / kMinChunk, (int64_t)cus * 2);
+                    grid = std::max<int64_t>(grid, 1);
+                    const int64_t chunk = (((n_groups + grid - 1) / grid) + 3) & ~int64_t(3);
+                    grid = (n_groups + chunk - 1) / chunk;
+                    ServeArgs b{sl.d_frames, n_plain, n_groups, chunk};
+                    hipLaunchKernelGGL(serve_kernel, dim3((unsigned)grid), dim3(kServeBlock), 0, st, b);
+                }
+                // frames with regions: the one-stream passes, tree into the ring slot
+                for (int p = n_plain; ok && p < n; ++p) {
+                    const SchedFrame &fr = F[sl.order[p]];
+                    const StreamDev &sd = D[fr.stream];
+                    uint32_t *slot = reinterpret_cast<uint32_t *>(sched.S[fr.stream].ring) +
+                                     (int64_t)fr.slot * sd.words * sd.n_regions;
+                    const uint32_t *leaf = reinterpret_cast<const uint32_t *>(sched.S[fr.stream].leaf);
+                    ok = (fr.test ? obg_classify(&sd.geom, fr.rgb, 1, leaf, fr.mask, slot, st)
+                                  : obg_train_frame(&sd.geom, fr.rgb, 1, slot, nullptr, st)) == OBG_OK;
+                }
+                if (ok && n_jobs) {
                     int maxw = 1;
                     for (int i = 0; i < n_jobs; ++i) maxw = std::max(maxw, sl.h_jobs[i].words);
                     hipLaunchKernelGGL(serve_merge_kernel, dim3((maxw + 255) / 256, n_jobs), dim3(256), 0, st,
                                        (const MergeJobDev *)sl.d_jobs);
                 }
-                ok = hipEventRecord(sl.k1, st) == hipSuccess;
-                const int nc = n - nt;
-                if (ok && nc && cfg->checksums) {
+                for (const SchedMerge &m : sl.batch.merges) {
+                    if (!ok || !D[m.stream].region) continue;
+                    const StreamDev &sd = D[m.stream];
+                    ok = obg_merge(&sd.geom, reinterpret_cast<const uint32_t *>(sched.S[m.stream].ring),
+                                   sched.S[m.stream].ring_len, m.first, m.n, sd.cfg.thr_num, sd.cfg.thr_den,
+                                   reinterpret_cast<uint32_t *>(sched.S[m.stream].leaf), st) == OBG_OK;
+                }
+                if (ok) ok = hipEventRecord(sl.k1, st) == hipSuccess;
+                const int nc = n_test_end - nt;
+                if (ok && nc > 0 && cfg->checksums) {
                     ok = hipMemsetAsync(sl.d_sum, 0, sizeof(unsigned long long) * nc, st) == hipSuccess;
                     hipLaunchKernelGGL(serve_checksum_kernel, dim3(16, nc), dim3(256), 0, st,
                                        (const ServeFrameDev *)(sl.d_frames + nt), sl.d_sum);
@@ -460,8 +513,8 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 for (int w = 0; ok && w < cfg->n_watch; ++w) {
                     const int s = cfg->watch_streams[w];
                     const uint64_t mbytes = sched.S[s].mask_bytes;
-                    for (int i = nt; ok && i < n; ++i) {
-                        const SchedFrame &fr = F[i];
+                    for (int p = nt; ok && p < n_test_end; ++p) {
+                        const SchedFrame &fr = F[sl.order[p]];
                         const int t = fr.frame - D[s].cfg.n_train;
                         if (fr.stream == s && t < cfg->watch_max_frames)
                             ok = hipMemcpyAsync(cfg->watch_masks[w] + (int64_t)t * (int64_t)(mbytes / 8), fr.mask, mbytes,
@@ -477,7 +530,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             }
             sl.busy = true;
             ++batches;
-            merges += n_jobs;
+            merges += (int64_t)sl.batch.merges.size();
             launched = true;
         }
         if (launched || progressed) idle_since = -1;

@@ -34,6 +34,7 @@ namespace obg {
 
 struct SchedStream {
     int32_t width, height, depth, n_train;
+    int32_t n_regions;          // trees per frame (1 without regions)
 };
 
 struct SchedFrame {
@@ -62,9 +63,10 @@ inline uint64_t sched_frame_bytes(const SchedStream &c) {
 inline uint64_t sched_mask_bytes(const SchedStream &c) {
     return (uint64_t)c.height * (uint64_t)((c.width + 63) / 64) * 8u;
 }
+// Bytes of one frame's trees (one ring slot): n_regions bitsets.
 inline uint64_t sched_tree_bytes(const SchedStream &c) {
     const uint64_t keys = 1ull << (3 * c.depth);
-    return keys < 32 ? 4 : keys / 8;
+    return (keys < 32 ? 4 : keys / 8) * (uint64_t)(c.n_regions > 0 ? c.n_regions : 1);
 }
 
 class ServeScheduler {

@@ -61,7 +61,8 @@ class BatchInfo(ctypes.Structure):
 
 class ServeStream(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("depth", ctypes.c_int32),
-                ("n_train", ctypes.c_int32), ("thr_num", ctypes.c_uint32), ("thr_den", ctypes.c_uint32)]
+                ("n_train", ctypes.c_int32), ("thr_num", ctypes.c_uint32), ("thr_den", ctypes.c_uint32),
+                ("region_w", ctypes.c_int32), ("region_h", ctypes.c_int32)]
 
 
 class ServeConfig(ctypes.Structure):
@@ -372,7 +373,8 @@ def obg_serve_run(streams, arrivals, ingest_fn: int, ingest_ctx: int, speed: flo
     n = len(streams)
     arr = (ServeStream * n)()
     for i, s in enumerate(streams):
-        arr[i] = ServeStream(s["width"], s["height"], s["depth"], s["n_train"], s["thr"][0], s["thr"][1])
+        arr[i] = ServeStream(s["width"], s["height"], s["depth"], s["n_train"], s["thr"][0], s["thr"][1],
+                             s.get("region_w", 0), s.get("region_h", 0))
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in arrivals]
     ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
     counts = (ctypes.c_int32 * n)(*[len(a) for a in arrs])

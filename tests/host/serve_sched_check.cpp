@@ -78,7 +78,7 @@ int main() {
         std::vector<int> n_frames(ns);
         uint64_t state = 0, largest = 0;
         for (int s = 0; s < ns; ++s) {
-            cfg[s] = {rint(1, 200), rint(1, 40), rint(1, 6), rint(1, 12)};
+            cfg[s] = {rint(1, 200), rint(1, 40), rint(1, 6), rint(1, 12), rint(0, 3) == 0 ? rint(2, 9) : 1};
             n_frames[s] = cfg[s].n_train + rint(0, 40);
             const uint64_t tb = sched_tree_bytes(cfg[s]);
             const int R = std::max(cfg[s].n_train, window);
