@@ -100,10 +100,33 @@ def workload(name, n_test):
     return S.cfg0()
 
 
+def host_cpu():
+    """Threads the host gives this process (capped by OMP_NUM_THREADS) and the
+    CPU's model name."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        n = min(n, int(os.environ.get("OMP_NUM_THREADS", n)))
+    except ValueError:
+        pass
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(n, 1), model
+
+
 def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, budget_s):
     """The oracle as it is, single-threaded: trees of every training frame, the
     merge, then test frames (fetched one at a time) until `budget_s` seconds
-    have passed or `n_test` frames are classified."""
+    have passed or `n_test` frames are classified.  A second leg classifies up
+    to 8 frames per host thread with the same model on all the host's threads
+    (the oracle's C calls release the GIL); it is reported beside the
+    single-threaded figure."""
     from oracle import octree
     t0 = time.perf_counter()
     f = octree.Forest(spec.width, spec.height, depth, region[0], region[1])
@@ -120,12 +143,26 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
         done += 1
     dt = t_train + t_cls
     px = (len(host_train) + done) * spec.pixels
-    return {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(host_train)} training frames (trees + merge, {t_train:.1f} s) and {done} test "
-                      f"frames (classify, {t_cls:.1f} s) of the same stream, {spec.width}x{spec.height}, "
-                      f"single-threaded",
-            "train_gpixel_s": round(len(host_train) * spec.pixels / t_train / 1e9, 5),
-            "classify_gpixel_s": round(done * spec.pixels / t_cls / 1e9, 5) if done else None}
+    threads, cpu_model = host_cpu()
+    out = {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+           "sample": f"{len(host_train)} training frames (trees + merge, {t_train:.1f} s) and {done} test "
+                     f"frames (classify, {t_cls:.1f} s) of the same stream, {spec.width}x{spec.height}, "
+                     f"single-threaded",
+           "train_gpixel_s": round(len(host_train) * spec.pixels / t_train / 1e9, 5),
+           "classify_gpixel_s": round(done * spec.pixels / t_cls / 1e9, 5) if done else None,
+           "cpu_model": cpu_model, "host_threads": threads}
+    if threads > 1 and done:
+        from concurrent.futures import ThreadPoolExecutor
+        frames = [test_frame(i) for i in range(min(done, 8 * threads))]
+        with ThreadPoolExecutor(threads) as ex:
+            list(ex.map(model.classify, frames[:threads]))
+            t1 = time.perf_counter()
+            list(ex.map(model.classify, frames))
+            t_mt = time.perf_counter() - t1
+        out["threaded_classify"] = {"threads": threads, "frames": len(frames),
+                                    "seconds": round(t_mt, 3),
+                                    "gpixel_s": round(len(frames) * spec.pixels / t_mt / 1e9, 5)}
+    return out
 
 
 def run_batched(a):
@@ -418,6 +455,7 @@ def run_served(a):
         ok = bool(wmasks) and all(np.array_equal(wmasks[0][i], got[i]) for i in range(len(got)))
         px = (sp.n_train + len(got)) * sp.width * sp.height
         out["cpu_baseline"] = {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+                               "cpu_model": host_cpu()[1],
                                "sample": f"stream {small} ({sp.width}x{sp.height}, d={depths[small]}): "
                                          f"{sp.n_train} training frames and the first {len(got)} served test "
                                          f"frames with re-merges, {dt:.1f} s single-threaded",

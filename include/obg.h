@@ -346,6 +346,13 @@ int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
  *   OBG_TUNE_MASK_STAGE         1 = gather a work item's mask in LDS and write
  *                               it in one run (items of <= 1024 groups;
  *                               default), 2 = write each 64-pixel word directly
+ *   OBG_TUNE_REGION_CHUNKS      1 = with regions, cut rows of regions into
+ *                               chunks of whole region columns when a call
+ *                               has too few rows of regions to fill the chip,
+ *                               and give passes that build occupancy one work
+ *                               item per (frame, chunk) whose words are
+ *                               stored (default); 2 = chunks only where a
+ *                               row's tables do not fit in LDS
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1
@@ -356,7 +363,8 @@ int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
 #define OBG_TUNE_LAYOUT              6
 #define OBG_TUNE_INTERLEAVE          7
 #define OBG_TUNE_MASK_STAGE          8
-#define OBG_TUNE_COUNT               9
+#define OBG_TUNE_REGION_CHUNKS       9
+#define OBG_TUNE_COUNT               10
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 

@@ -127,6 +127,14 @@ size_t strip_lds_max() {
 // order: the wide one when it fits, else the compact one.
 constexpr int64_t kOccItemsPerWg = 4;
 
+// Region columns per chunk must cover whole 64-pixel mask words: the
+// smallest such number of columns.
+int chunk_step(const Geo &g) {
+    const int rw16 = g.region_w / 16;
+    int gcd = rw16 % 4 == 0 ? 4 : (rw16 % 2 == 0 ? 2 : 1);
+    return 4 / gcd;
+}
+
 bool strip_ok(const Geo &g, int mode, int *lay) {
     if (g.depth > 6) return false;
     if (g.region_w && (g.region_w % 16) != 0) return false;
@@ -138,23 +146,49 @@ bool strip_ok(const Geo &g, int mode, int *lay) {
         return true;
     }
     *lay = LAY_COMPACT;
-    const size_t cap = g.reg_cols > 1 ? strip_lds_max() : 64 * 1024;
-    return strip_lds_bytes(g.depth, mode, g.reg_cols, LAY_COMPACT) <= cap;
+    if (g.reg_cols == 1) return strip_lds_bytes(g.depth, mode, 1, LAY_COMPACT) <= 64 * 1024;
+    // rows of regions are cut into chunks when their tables do not fit: the
+    // narrowest chunk has to
+    const int narrow = std::min(g.reg_cols, chunk_step(g));
+    return strip_lds_bytes(g.depth, mode, narrow, LAY_COMPACT) <= strip_lds_max();
+}
+
+// Region columns per chunk of a row of regions: the fewest chunks whose
+// tables take at most 64 KiB of LDS (so that two workgroups share a CU) and,
+// when the call's rows of regions are fewer than `target` work items, enough
+// chunks to give about `target` of them.  Every chunk but the last spans
+// chunk_cols columns, a multiple of chunk_step.
+int region_chunk_cols(const Geo &g, int mode, int lay, int64_t rows_sf, int64_t target) {
+    const int step = chunk_step(g);
+    if (g.reg_cols <= step) return g.reg_cols;
+    const int max_chunks = g.reg_cols / step;
+    int64_t n = 1;
+    const size_t row = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
+    const size_t cap = std::min<size_t>(64 * 1024, strip_lds_max());
+    if (row > cap) n = (int64_t)((row + cap - 1) / cap);
+    if (tune(OBG_TUNE_REGION_CHUNKS, 1) == 1 && rows_sf < target)
+        n = std::max<int64_t>(n, (target + rows_sf - 1) / rows_sf);
+    n = std::min<int64_t>(n, max_chunks);
+    int cols = (int)((g.reg_cols + n - 1) / n);
+    cols = (cols + step - 1) / step * step;
+    // the chunk must fit the workgroup's LDS (strip_ok guarantees `step` does)
+    while (cols > step && strip_lds_bytes(g.depth, mode, cols, lay) > strip_lds_max()) cols -= step;
+    return cols >= g.reg_cols ? g.reg_cols : cols;
 }
 
 int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, const uint32_t *leaf,
                uint64_t *mask, uint32_t *occ, uint32_t *counts, hipStream_t st) {
     hipError_t e;
     const int64_t occ_words = (int64_t)n_frames * g.n_regions * g.words;
-    if (mode & MODE_OCC) {
-        if ((e = launch_fill_u32(occ, occ_words, 0u, st)) != hipSuccess) return hip_fail(e, "zero occupancy");
-    }
     if (mode & MODE_COUNTS) {
         const int64_t n = (int64_t)n_frames * g.n_regions * leaf_count(g.depth);
         if ((e = launch_fill_u32(counts, n, 0u, st)) != hipSuccess) return hip_fail(e, "zero counts");
     }
     int lay = LAY_COMPACT;
     if (!strip_ok(g, mode, &lay)) {
+        if (mode & MODE_OCC) {
+            if ((e = launch_fill_u32(occ, occ_words, 0u, st)) != hipSuccess) return hip_fail(e, "zero occupancy");
+        }
         GenericArgs a{};
         a.rgb = rgb;
         a.frame_pitch = g.frame_pitch;
@@ -190,18 +224,34 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.n_regions = g.n_regions;
     a.div_gpr = make_fastdiv((uint32_t)a.gpr);
     a.div_tile = make_fastdiv(g.region_w ? (uint32_t)(g.region_w / 16) : (uint32_t)a.gpr);
-    const int64_t groups_strip = (int64_t)a.strip_rows * a.gpr;
-    if (groups_strip > (1LL << 30)) return fail(OBG_EINVAL, "frame too large");
+    const int cus = cu_count();
+    // rows of regions cut into chunks of whole region columns
+    a.chunk_cols = g.reg_cols;
+    a.n_chunks = 1;
+    a.cgpr = a.cgpr_last = a.gpr;
+    if (g.reg_cols > 1) {
+        a.chunk_cols = region_chunk_cols(g, mode, lay, (int64_t)a.n_strips * n_frames, 2LL * cus);
+        a.n_chunks = (g.reg_cols + a.chunk_cols - 1) / a.chunk_cols;
+        if (a.n_chunks > 1) {
+            a.cgpr = a.chunk_cols * (g.region_w / 16);
+            a.cgpr_last = a.gpr - (a.n_chunks - 1) * a.cgpr;
+            if (a.cgpr % 4 || a.cgpr_last % 4 || a.cgpr_last < 1 || a.cgpr_last > a.cgpr)
+                return fail(OBG_EINVAL, "internal: bad region chunk (%d columns)", a.chunk_cols);
+        }
+        if ((int64_t)a.n_strips * a.n_chunks > 0x7FFFFFFF) return fail(OBG_EINVAL, "too many regions");
+        a.n_strips *= a.n_chunks;
+    }
+    a.div_cgpr = make_fastdiv((uint32_t)a.cgpr);
+    a.div_cgpr_last = make_fastdiv((uint32_t)a.cgpr_last);
+    const int64_t groups_strip = (int64_t)a.strip_rows * a.cgpr;
+    if ((int64_t)a.strip_rows * a.gpr > (1LL << 30)) return fail(OBG_EINVAL, "frame too large");
     const bool occ_only = (mode & MODE_MASK) == 0;
     // classify: large tables leave room for few workgroups per CU; 512-thread
     // groups keep the CU at its 32 waves with 4 of them
-    const size_t lds_need = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
     const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024) : tune(OBG_TUNE_CLASSIFY_BLOCK, 512);
-    (void)lds_need;
     if (occ_only && block != 256 && block != 1024) return fail(OBG_EINVAL, "train block size must be 256 or 1024");
     if (!occ_only && block != 256 && block != 512) return fail(OBG_EINVAL, "classify block size must be 256 or 512");
-    const size_t lds = strip_lds_bytes(g.depth, mode, g.reg_cols, lay);
-    const int cus = cu_count();
+    const size_t lds = strip_lds_bytes(g.depth, mode, a.chunk_cols, lay);
     // workgroups per CU: LDS and the 32 waves of a CU bound it
     int per_cu = lds ? (int)((160 * 1024) / lds) : 32;
     const int wave_cap = 32 / (block / 64);
@@ -210,7 +260,16 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     const int64_t n_sf = (int64_t)a.n_strips * n_frames;
     int64_t spans;
     int64_t target;
-    if (mode & MODE_OCC) {
+    bool store = false;
+    if ((mode & MODE_OCC) && g.reg_cols > 1 && 2 * n_sf >= (int64_t)cus &&
+        tune(OBG_TUNE_REGION_CHUNKS, 1) == 1) {
+        // one work item per (frame, chunk): enough of them, and each one's
+        // occupancy words are written by one workgroup, so they are stored
+        // (no zero fill, no atomics)
+        target = (int64_t)cus * std::min(per_cu, tune(OBG_TUNE_OCC_WG_PER_CU, block == 1024 ? 2 : 4));
+        spans = 1;
+        store = true;
+    } else if (mode & MODE_OCC) {
         // each (frame, strip) segment of a workgroup costs one LDS flush:
         // few, large items
         int want = tune(OBG_TUNE_OCC_WG_PER_CU, block == 1024 ? 2 : 4);
@@ -252,7 +311,9 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.interleave = (g.reg_cols == 1 && a.n_strips == 1 && !(mode & MODE_OCC))
                        ? (tune(OBG_TUNE_INTERLEAVE, 1) == 1)
                        : (tune(OBG_TUNE_INTERLEAVE, 2) == 1);
-    a.stage_mask = ((mode & MODE_MASK) && span <= 1024) ? (tune(OBG_TUNE_MASK_STAGE, 1) == 1) : 0;
+    // staging writes an item's mask as one run: whole rows only
+    a.stage_mask = ((mode & MODE_MASK) && span <= 1024 && a.n_chunks == 1) ? (tune(OBG_TUNE_MASK_STAGE, 1) == 1) : 0;
+    a.occ_store = store ? 1 : 0;
     // reading before the atomic pays when many pixels share few keys (measured
     // at 1080p: 25 % faster trees at d = 3, even at d = 5, slower at d = 6 and
     // with regions)
@@ -265,6 +326,9 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.mask_row_words = g.mask_row_words;
     a.occ = occ;
     a.counts = counts;
+    if ((mode & MODE_OCC) && !store) {
+        if ((e = launch_fill_u32(occ, occ_words, 0u, st)) != hipSuccess) return hip_fail(e, "zero occupancy");
+    }
     const int grid = (int)(n_items < target ? n_items : target);
     // one region per strip: the kernel's tables are static, no dynamic LDS
     const size_t dyn_lds = g.reg_cols > 1 ? lds : 0;

@@ -17,21 +17,27 @@ struct StripArgs {
     int32_t width, height, n_frames;
     int32_t gpr;              // 16-pixel groups per row: 4 * ceil(width / 64)
     int32_t strip_rows;       // rows per strip (region_h, or height)
-    int32_t n_strips;
-    int32_t reg_cols;         // regions per strip (1 without regions)
+    int32_t n_strips;         // region rows x chunks
+    int32_t reg_cols;         // regions per row of regions (1 without regions)
     int32_t n_regions;
     FastDiv div_gpr;          // group-in-strip -> row-in-strip
     FastDiv div_tile;         // group-in-row -> region column (region_w / 16 groups)
+    // chunks of a row of regions (regions only; one chunk = the whole row):
+    // chunk k holds region columns k*chunk_cols .. and group columns
+    // k*cgpr .. (the last chunk runs to the end of the row, cgpr_last groups)
+    int32_t n_chunks, chunk_cols, cgpr, cgpr_last;
+    FastDiv div_cgpr, div_cgpr_last;
     int32_t span;             // groups per work item
     int32_t spans;            // work items per (strip, frame)
     int32_t n_items;          // n_strips * n_frames * spans
     int32_t interleave;       // 1: item i goes to workgroup i % grid; 0: contiguous ranges
     int32_t stage_mask;       // 1: masks gathered in LDS per item (span <= 1024 groups)
     int32_t occ_test;         // 1: read an occupancy word first, atomic OR only when the bit is clear
+    int32_t occ_store;        // 1: one work item per (frame, strip): occupancy words are stored, not OR-ed
     const uint32_t *leaf;     // [n_regions][words], key order
     uint64_t *mask;           // [n_frames][height][mask_row_words]
     int32_t mask_row_words;
-    uint32_t *occ;            // [n_frames][n_regions][words], zeroed, OR-ed into
+    uint32_t *occ;            // [n_frames][n_regions][words], zeroed and OR-ed into (or stored)
     uint32_t *counts;         // [n_frames][n_regions][8^d], zeroed, added into
 };
 

@@ -44,9 +44,11 @@ strip_kernel(StripArgs a) {
     __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
     uint16_t *stage = (MASK && a.stage_mask) ? st_mask : nullptr;
     const int tid = threadIdx.x;
-    const int tiles = REGION ? a.reg_cols : 1;
+    // LDS tables of one strip: a chunk of at most chunk_cols regions
+    const int max_tiles = REGION ? a.chunk_cols : 1;
     uint32_t *leaf_lds = REGION ? dyn_lds : st_leaf;
-    uint32_t *occ_lds = REGION ? dyn_lds + (MASK ? tiles * LW : 0) : st_occ;
+    uint32_t *occ_lds = REGION ? dyn_lds + (MASK ? max_tiles * LW : 0) : st_occ;
+    const bool store = a.occ_store != 0;
 
     // work items: a contiguous range per workgroup, or interleaved so that
     // the items in flight at any moment are neighbours in memory
@@ -60,22 +62,39 @@ strip_kernel(StripArgs a) {
         i1 = (int)((int64_t)a.n_items * (blockIdx.x + 1) / gridDim.x);
         istep = 1;
     }
-    int cur_s = -1, cur_f = -1;
+    // the segment (frame, strip) whose occupancy the LDS table holds: its
+    // frame, strip, first region and number of regions
+    int cur_s = -1, cur_f = -1, cur_tiles = 1;
+    int64_t cur_reg0 = 0;
     for (int it = i0; it < i1; it += istep) {
         const int sf = it / a.spans;
         const int t = it - sf * a.spans;
         const int s = sf / a.n_frames;
         const int f = sf - s * a.n_frames;
+        // strip s = (row of regions rr, chunk k)
+        int rr = s;
+        Chunk ch{};
+        if (REGION) {
+            rr = s / a.n_chunks;
+            const int k = s - rr * a.n_chunks;
+            const bool last = k == a.n_chunks - 1;
+            ch.div = last ? a.div_cgpr_last : a.div_cgpr;
+            ch.cw = (uint32_t)(last ? a.cgpr_last : a.cgpr);
+            ch.gx0 = (uint32_t)k * (uint32_t)a.cgpr;
+            ch.c0 = k * a.chunk_cols;
+            ch.tiles = min(a.chunk_cols, a.reg_cols - ch.c0);
+        }
+        const int tiles = REGION ? ch.tiles : 1;
+        const int64_t reg0 = REGION ? (int64_t)rr * a.reg_cols + ch.c0 : (int64_t)s;
         const bool new_seg = (s != cur_s) || (f != cur_f);
         if (OCC && new_seg && cur_f >= 0) {
             __syncthreads();
-            occ_from_lds<D, PAD>(occ_lds,
-                                 a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * tiles) * KW,
-                                 tiles, tid, BLOCK);
+            occ_from_lds<D, PAD>(occ_lds, a.occ + ((int64_t)cur_f * a.n_regions + cur_reg0) * KW, cur_tiles, tid,
+                                 BLOCK, store);
         }
         if (MASK && s != cur_s) {
             __syncthreads();
-            leaf_to_lds<D, PAD>(a.leaf + (int64_t)s * tiles * KW, leaf_lds, tiles, tid, BLOCK);
+            leaf_to_lds<D, PAD>(a.leaf + reg0 * KW, leaf_lds, tiles, tid, BLOCK);
         }
         if (OCC && new_seg) {
             __syncthreads();
@@ -84,10 +103,12 @@ strip_kernel(StripArgs a) {
         }
         cur_s = s;
         cur_f = f;
+        cur_tiles = tiles;
+        cur_reg0 = reg0;
 
-        const int row0 = s * a.strip_rows;
+        const int row0 = rr * a.strip_rows;
         const int rows = min(a.strip_rows, a.height - row0);
-        const int gcount = rows * a.gpr;
+        const int gcount = rows * (REGION ? (int)ch.cw : a.gpr);
         const int gb = t * a.span;
         const int ge = min(gb + a.span, gcount);
         const int64_t strip_off = (int64_t)row0 * a.row_pitch;
@@ -97,15 +118,13 @@ strip_kernel(StripArgs a) {
         if (MASK)
             ms = make_rsrc(a.mask + ((int64_t)f * a.height + row0) * a.mask_row_words,
                            (uint32_t)rows * (uint32_t)a.mask_row_words * 8u);
-        uint32_t *cbase = CNT ? a.counts + ((int64_t)f * a.n_regions + (int64_t)s * tiles) * LC
-                              : nullptr;
-        span_loop<D, MODE, PAD, REGION, BLOCK>(a, rs, ms, gb, ge, leaf_lds, occ_lds, cbase, stage);
+        uint32_t *cbase = CNT ? a.counts + ((int64_t)f * a.n_regions + reg0) * LC : nullptr;
+        span_loop<D, MODE, PAD, REGION, BLOCK>(a, rs, ms, gb, ge, leaf_lds, occ_lds, cbase, stage, ch);
     }
     if (OCC && cur_f >= 0) {
         __syncthreads();
-        occ_from_lds<D, PAD>(occ_lds,
-                             a.occ + ((int64_t)cur_f * a.n_regions + (int64_t)cur_s * tiles) * KW,
-                             tiles, tid, BLOCK);
+        occ_from_lds<D, PAD>(occ_lds, a.occ + ((int64_t)cur_f * a.n_regions + cur_reg0) * KW, cur_tiles, tid,
+                             BLOCK, store);
     }
 }
 

@@ -39,9 +39,12 @@ __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, u
     __syncthreads();
 }
 
+// store: every output word belongs to this workgroup alone (one work item per
+// segment), so it is written as is; otherwise set bits are OR-ed into words
+// other workgroups also write.
 template <int D, int PAD>
 __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__restrict__ occ,
-                                             int n_tiles, int tid, int nt) {
+                                             int n_tiles, int tid, int nt, bool store = false) {
     constexpr int KW = leaf_words(D);
     constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
@@ -57,7 +60,10 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
             const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
             out |= ((tile[l >> 5] >> (l & 31)) & 1u) << b;
         }
-        if (out) atomicOr(&occ[i], out);
+        if (store)
+            occ[i] = out;
+        else if (out)
+            atomicOr(&occ[i], out);
     }
 }
 
@@ -78,11 +84,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, ui
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// The part of a strip that a work item walks.  With several regions per
+// strip, a strip may be cut into chunks of whole region columns, so that a
+// workgroup holds the tables of fewer regions and one frame still gives many
+// work items; group g of a chunk is row g / cw, column gx0 + g % cw.
+struct Chunk {
+    FastDiv div;      // divides by cw
+    uint32_t cw;      // groups per row of the chunk (a multiple of 4)
+    uint32_t gx0;     // the chunk's first group column (a multiple of 4)
+    int32_t c0;       // the chunk's first region column
+    int32_t tiles;    // region columns in the chunk
+};
+
 // Issue the three 16-byte loads of group g (16 pixels = 48 bytes).
-__device__ __forceinline__ void fetch_group(__amdgpu_buffer_rsrc_t rs, const StripArgs &a, int g,
-                                            uint32_t (&u)[12], uint32_t &yr, uint32_t &gx) {
-    yr = fdiv((uint32_t)g, a.div_gpr);
-    gx = (uint32_t)g - yr * (uint32_t)a.gpr;
+template <bool REGION>
+__device__ __forceinline__ void fetch_group(__amdgpu_buffer_rsrc_t rs, const StripArgs &a, const Chunk &ch,
+                                            int g, uint32_t (&u)[12], uint32_t &yr, uint32_t &gx) {
+    if (REGION) {
+        yr = fdiv((uint32_t)g, ch.div);
+        gx = (uint32_t)g - yr * ch.cw + ch.gx0;
+    } else {
+        yr = fdiv((uint32_t)g, a.div_gpr);
+        gx = (uint32_t)g - yr * (uint32_t)a.gpr;
+    }
     const uint32_t off = yr * (uint32_t)a.row_pitch + 48u * gx;
     const v4u v0 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
     const v4u v1 = __builtin_bit_cast(v4u, __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16, 0, 0));
@@ -133,7 +157,7 @@ __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nv
 }
 
 template <int D, int MODE, int PAD, bool REGION>
-__device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffer_rsrc_t ms,
+__device__ __forceinline__ void consume_group(const StripArgs &a, const Chunk &ch, __amdgpu_buffer_rsrc_t ms,
                                               const uint32_t (&u)[12], uint32_t yr, uint32_t gx,
                                               const uint32_t *leaf_lds, uint32_t *occ_lds,
                                               uint32_t *__restrict__ cbase, uint16_t *stage, int gl) {
@@ -145,8 +169,8 @@ __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffe
     nv = nv < 0 ? 0 : (nv > 16 ? 16 : nv);
     int c = 0;
     if (REGION) {
-        c = (int)fdiv(gx, a.div_tile);
-        c = c < a.reg_cols ? c : a.reg_cols - 1;     // padding groups: result discarded
+        c = (int)fdiv(gx, a.div_tile) - ch.c0;
+        c = c < ch.tiles ? c : ch.tiles - 1;        // padding groups: result discarded
     }
     const uint32_t *leaf_tile = leaf_lds + c * LW;
     uint32_t *occ_tile = occ_lds + c * LW;
@@ -182,24 +206,26 @@ __device__ __forceinline__ void consume_group(const StripArgs &a, __amdgpu_buffe
 // The groups [gb, ge) of one (frame, strip): two groups in flight per lane
 // (the next group's loads are issued before the current one is worked on);
 // with `stage`, the span's mask is gathered in LDS and written as one run.
+// Without regions `ch` is not read (the strip is whole rows).
 template <int D, int MODE, int PAD, bool REGION, int BLOCK>
 __device__ __forceinline__ void span_loop(const StripArgs &a, __amdgpu_buffer_rsrc_t rs,
                                           __amdgpu_buffer_rsrc_t ms, int gb, int ge,
                                           const uint32_t *leaf_lds, uint32_t *occ_lds,
-                                          uint32_t *__restrict__ cbase, uint16_t *stage) {
+                                          uint32_t *__restrict__ cbase, uint16_t *stage,
+                                          const Chunk &ch = Chunk{}) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     const int tid = threadIdx.x;
     uint32_t ua[12], ub[12], ya = 0, xa = 0, yb = 0, xb = 0;
     int g = gb + tid;
-    if (g < ge) fetch_group(rs, a, g, ua, ya, xa);
+    if (g < ge) fetch_group<REGION>(rs, a, ch, g, ua, ya, xa);
     for (; g < ge; g += 2 * BLOCK) {
         const int g1 = g + BLOCK;
-        if (g1 < ge) fetch_group(rs, a, g1, ub, yb, xb);
-        consume_group<D, MODE, PAD, REGION>(a, ms, ua, ya, xa, leaf_lds, occ_lds, cbase, stage, g - gb);
+        if (g1 < ge) fetch_group<REGION>(rs, a, ch, g1, ub, yb, xb);
+        consume_group<D, MODE, PAD, REGION>(a, ch, ms, ua, ya, xa, leaf_lds, occ_lds, cbase, stage, g - gb);
         const int g2 = g + 2 * BLOCK;
-        if (g2 < ge) fetch_group(rs, a, g2, ua, ya, xa);
+        if (g2 < ge) fetch_group<REGION>(rs, a, ch, g2, ua, ya, xa);
         if (g1 < ge)
-            consume_group<D, MODE, PAD, REGION>(a, ms, ub, yb, xb, leaf_lds, occ_lds, cbase, stage, g1 - gb);
+            consume_group<D, MODE, PAD, REGION>(a, ch, ms, ub, yb, xb, leaf_lds, occ_lds, cbase, stage, g1 - gb);
     }
     if (MASK && stage) {
         // group g's 16 mask bits are bytes 2g, 2g+1 of the strip's mask, so

@@ -274,7 +274,8 @@ def obg_score(g: FrameGeom, mask: torch.Tensor, truth: torch.Tensor, n_frames: i
 
 
 TUNE_KEYS = {"train_block": 0, "occ_blind": 1, "occ_wg_per_cu": 2,
-             "classify_wg_per_cu": 3, "classify_span": 4, "classify_block": 5, "layout": 6, "interleave": 7, "mask_stage": 8}
+             "classify_wg_per_cu": 3, "classify_span": 4, "classify_block": 5, "layout": 6, "interleave": 7, "mask_stage": 8,
+             "region_chunks": 9}
 
 
 def obg_tune_set(key, value: int):

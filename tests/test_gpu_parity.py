@@ -275,6 +275,60 @@ def test_fused_classify_occupancy(env):
         assert torch.equal(occ_t, occ_c)
 
 
+@pytest.mark.parametrize("W,H,d,rw,rh", [(1280, 720, 4, 32, 32), (1000, 200, 5, 48, 40), (1010, 64, 3, 16, 16),
+                                         (3840, 64, 4, 32, 32), (640, 96, 6, 32, 32), (1920, 128, 5, 64, 64)])
+def test_region_chunks_one_frame_per_call(env, W, H, d, rw, rh):
+    """Calls of one frame with regions cut each row of regions into chunks of
+    whole region columns (the last one ragged, with the row's padding), and a
+    call of a few frames too: trees, pixel counts, masks and fused trees equal
+    the oracle's whatever the output buffers held before (stored trees must
+    cover every word)."""
+    obg, O = env
+    rng = np.random.default_rng(W + H + d)
+    rp = ((3 * W + 15) // 16) * 16
+    T = 3
+    frames = brute.tiny_frames(rng, T + 2, W, H, n_colours=20, row_pitch=rp)
+    g = obg.FrameGeom(W, H, d, region_w=rw, region_h=rh)
+    print(f"[case] region chunks W={W} H={H} d={d} region={rw}x{rh}", flush=True)
+    dev = upload(frames, g.frame_pitch)
+    f = O.Forest(W, H, d, rw, rh)
+    idx = f.add_frames(frames)
+    want = [f.export(i, with_counts=True) for i in idx]
+    model = f.merge(idx[:T], 1, 2)
+    # one frame per call, outputs full of ones beforehand
+    occ = obg.empty_occ(g, T + 2).fill_(-1)
+    for i in range(T):
+        obg.obg_train_frame(g, dev[i:i + 1], 1, occ[i:i + 1])
+    leaf = obg.empty_leafset(g).fill_(-1)
+    obg.obg_merge(g, occ, T, 0, T, 1, 2, leaf)
+    mask = obg.empty_mask(g, 2).fill_(-1)
+    for i in range(2):
+        obg.obg_classify(g, dev[T + i:T + i + 1], 1, leaf, mask[i:i + 1], occ[T + i:T + i + 1])
+    torch.cuda.synchronize()
+    for i in range(T + 2):
+        assert np.array_equal(u32(occ[i]).reshape(want[i][0].shape), want[i][0]), f"trees of frame {i}"
+    assert np.array_equal(u32(leaf).reshape(model.n_regions, -1), model.leafset()), "leaf set"
+    for i in range(2):
+        w = model.classify(frames[T + i])
+        assert np.array_equal(u64(mask[i]).reshape(w.shape), w), f"mask of frame {i}"
+    # all frames in one call, with pixel counts where they fit
+    occ2 = obg.empty_occ(g, T + 2).fill_(-1)
+    cnt = None
+    if d <= 5:
+        cnt = torch.full((T + 2, g.n_regions, 1 << (3 * d)), -1, dtype=torch.int32, device="cuda")
+    obg.obg_train_frame(g, dev, T + 2, occ2, cnt)
+    mask2 = obg.empty_mask(g, 2).fill_(-1)
+    occ3 = obg.empty_occ(g, 2).fill_(-1)
+    obg.obg_classify(g, dev[T:], 2, leaf, mask2, occ3)
+    torch.cuda.synchronize()
+    assert torch.equal(occ2, occ), "trees: one call differs from calls of one frame"
+    assert torch.equal(occ3, occ[T:]), "fused trees of two frames"
+    assert torch.equal(mask2, mask), "masks of two frames"
+    if cnt is not None:
+        for i in range(T + 2):
+            assert np.array_equal(u32(cnt[i]).reshape(want[i][1].shape), want[i][1]), f"counts of frame {i}"
+
+
 def test_repeat_runs_identical(env):
     """Results are exact integers; repeated launches must give identical bytes
     (a race in LDS or in the atomics would show here)."""
@@ -314,6 +368,7 @@ KNOBS = [
     {"occ_wg_per_cu": 1},
     {"occ_blind": 1},
     {"occ_blind": 2},
+    {"region_chunks": 2},
 ]
 
 
@@ -322,7 +377,7 @@ def test_launch_knobs_do_not_change_results(env, knobs):
     """Every launch shape gives the same bytes as the oracle (no LDS or atomic races)."""
     obg, O = env
     rng = np.random.default_rng(4242)
-    cases = [(160, 24, 4, 0, 0), (333, 17, 5, 0, 0), (96, 40, 3, 32, 16), (200, 30, 6, 0, 0)]
+    cases = [(160, 24, 4, 0, 0), (333, 17, 5, 0, 0), (96, 40, 3, 32, 16), (200, 30, 6, 0, 0), (480, 64, 4, 32, 32)]
     try:
         for k, v in knobs.items():
             obg.obg_tune_set(k, v)
