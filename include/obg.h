@@ -324,19 +324,23 @@ int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
  * (0 restores the built-in default).  They change speed only: every setting
  * gives the same bytes.
  *   OBG_TUNE_TRAIN_BLOCK        threads per workgroup of occupancy-only
- *                               passes: 256 or 1024 (default 1024)
+ *                               passes: 256 or 1024 (default 1024; 256 for
+ *                               region work items of fewer than 2048
+ *                               16-pixel groups)
  *   OBG_TUNE_OCC_BLIND          1 = set occupancy bits with an unconditional
- *                               LDS atomic OR (default with regions and at
- *                               d = 6), 2 = read the word first and OR only a
- *                               clear bit (default otherwise: fewer colliding
- *                               atomics when many pixels share a key)
+ *                               LDS atomic OR (default at d = 6 and for
+ *                               occupancy-only passes with regions), 2 = read
+ *                               the word first and OR only a clear bit
+ *                               (default otherwise: fewer colliding atomics
+ *                               when many pixels share a key)
  *   OBG_TUNE_OCC_WG_PER_CU      workgroups per CU of passes that build
  *                               occupancy (default 2 at 1024 threads, else 4)
  *   OBG_TUNE_CLASSIFY_WG_PER_CU workgroups per CU of classify-only passes
  *                               (default 2, fewer if LDS does not allow)
  *   OBG_TUNE_CLASSIFY_SPAN      16-pixel groups per work item (default 512)
- *   OBG_TUNE_CLASSIFY_BLOCK     threads per workgroup of classify-only
- *                               passes: 256 or 512 (default)
+ *   OBG_TUNE_CLASSIFY_BLOCK     threads per workgroup of classify passes:
+ *                               256 or 512 (default; 256 for fused region
+ *                               work items of fewer than 2048 groups)
  *   OBG_TUNE_LAYOUT             LDS order of d <= 5 trees: 1 = wide table
  *                               indexed by the pixel's R,G bytes (default),
  *                               2 = compact

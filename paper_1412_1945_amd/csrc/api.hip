@@ -246,9 +246,18 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     const int64_t groups_strip = (int64_t)a.strip_rows * a.cgpr;
     if ((int64_t)a.strip_rows * a.gpr > (1LL << 30)) return fail(OBG_EINVAL, "frame too large");
     const bool occ_only = (mode & MODE_MASK) == 0;
+    const int64_t n_sf = (int64_t)a.n_strips * n_frames;
+    // with regions, passes that build occupancy take one work item per
+    // (frame, chunk) when there are enough of them
+    const bool region_items = (mode & MODE_OCC) && g.reg_cols > 1 && 2 * n_sf >= (int64_t)cus &&
+                              tune(OBG_TUNE_REGION_CHUNKS, 1) == 1;
     // classify: large tables leave room for few workgroups per CU; 512-thread
-    // groups keep the CU at its 32 waves with 4 of them
-    const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, 1024) : tune(OBG_TUNE_CLASSIFY_BLOCK, 512);
+    // groups keep the CU at its 32 waves with 4 of them.  Small region items
+    // (a single 4K frame: about 1000 groups each) run faster in 256-thread
+    // groups (measured: 18 vs 27 us per frame for trees, 33 vs 35 us fused)
+    const bool small_items = region_items && groups_strip < 2048;
+    const int block = occ_only ? tune(OBG_TUNE_TRAIN_BLOCK, small_items ? 256 : 1024)
+                               : tune(OBG_TUNE_CLASSIFY_BLOCK, small_items ? 256 : 512);
     if (occ_only && block != 256 && block != 1024) return fail(OBG_EINVAL, "train block size must be 256 or 1024");
     if (!occ_only && block != 256 && block != 512) return fail(OBG_EINVAL, "classify block size must be 256 or 512");
     const size_t lds = strip_lds_bytes(g.depth, mode, a.chunk_cols, lay);
@@ -257,12 +266,10 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     const int wave_cap = 32 / (block / 64);
     if (per_cu > wave_cap) per_cu = wave_cap;
     if (per_cu < 1) per_cu = 1;
-    const int64_t n_sf = (int64_t)a.n_strips * n_frames;
     int64_t spans;
     int64_t target;
     bool store = false;
-    if ((mode & MODE_OCC) && g.reg_cols > 1 && 2 * n_sf >= (int64_t)cus &&
-        tune(OBG_TUNE_REGION_CHUNKS, 1) == 1) {
+    if (region_items) {
         // one work item per (frame, chunk): enough of them, and each one's
         // occupancy words are written by one workgroup, so they are stored
         // (no zero fill, no atomics)
@@ -315,9 +322,11 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.stage_mask = ((mode & MODE_MASK) && span <= 1024 && a.n_chunks == 1) ? (tune(OBG_TUNE_MASK_STAGE, 1) == 1) : 0;
     a.occ_store = store ? 1 : 0;
     // reading before the atomic pays when many pixels share few keys (measured
-    // at 1080p: 25 % faster trees at d = 3, even at d = 5, slower at d = 6 and
-    // with regions)
-    a.occ_test = tune(OBG_TUNE_OCC_BLIND, (g.reg_cols == 1 && g.depth <= 5) ? 2 : 1) == 2;
+    // at 1080p: 25 % faster trees at d = 3, even at d = 5, slower at d = 6;
+    // with 32x32 regions at 4K, d = 4: 21 % faster in the fused pass, 3 %
+    // slower for trees alone)
+    const bool read_first = g.depth <= 5 && (g.reg_cols == 1 || (mode & MODE_MASK));
+    a.occ_test = tune(OBG_TUNE_OCC_BLIND, read_first ? 2 : 1) == 2;
     a.span = (int32_t)span;
     a.spans = (int32_t)spans;
     a.n_items = (int32_t)n_items;
