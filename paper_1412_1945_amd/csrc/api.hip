@@ -176,8 +176,11 @@ int region_chunk_cols(const Geo &g, int mode, int lay, int64_t rows_sf, int64_t 
     return cols >= g.reg_cols ? g.reg_cols : cols;
 }
 
+// lists: frames, masks and trees through per-frame pointer arrays (the
+// geometry must pass strip_ok; every (frame, strip) is one work item and its
+// trees are stored whole)
 int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, const uint32_t *leaf,
-               uint64_t *mask, uint32_t *occ, uint32_t *counts, hipStream_t st) {
+               uint64_t *mask, uint32_t *occ, uint32_t *counts, hipStream_t st, const FrameLists *lists = nullptr) {
     hipError_t e;
     const int64_t occ_words = (int64_t)n_frames * g.n_regions * g.words;
     if (mode & MODE_COUNTS) {
@@ -186,6 +189,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     }
     int lay = LAY_COMPACT;
     if (!strip_ok(g, mode, &lay)) {
+        if (lists) return fail(OBG_EINVAL, "internal: frame lists need the LDS kernels");
         if (mode & MODE_OCC) {
             if ((e = launch_fill_u32(occ, occ_words, 0u, st)) != hipSuccess) return hip_fail(e, "zero occupancy");
         }
@@ -249,8 +253,8 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     const int64_t n_sf = (int64_t)a.n_strips * n_frames;
     // with regions, passes that build occupancy take one work item per
     // (frame, chunk) when there are enough of them
-    const bool region_items = (mode & MODE_OCC) && g.reg_cols > 1 && 2 * n_sf >= (int64_t)cus &&
-                              tune(OBG_TUNE_REGION_CHUNKS, 1) == 1;
+    const bool region_items = lists || ((mode & MODE_OCC) && g.reg_cols > 1 && 2 * n_sf >= (int64_t)cus &&
+                                        tune(OBG_TUNE_REGION_CHUNKS, 1) == 1);
     // classify: large tables leave room for few workgroups per CU; 512-thread
     // groups keep the CU at its 32 waves with 4 of them.  Small region items
     // (a single 4K frame: about 1000 groups each) run faster in 256-thread
@@ -335,6 +339,11 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
     a.mask_row_words = g.mask_row_words;
     a.occ = occ;
     a.counts = counts;
+    if (lists) {
+        a.rgb_list = lists->rgb;
+        a.mask_list = lists->mask;
+        a.occ_list = lists->occ;
+    }
     if ((mode & MODE_OCC) && !store) {
         if ((e = launch_fill_u32(occ, occ_words, 0u, st)) != hipSuccess) return hip_fail(e, "zero occupancy");
     }
@@ -347,6 +356,27 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
 }
 
 }  // namespace
+
+bool obg::pixels_list_ok(const obg_geom *g, int mode) {
+    Geo o{};
+    int lay = 0;
+    if (check_geom(g, &o, true) != OBG_OK) return false;
+    // the list kernels are the region ones: several regions per row
+    if (o.reg_cols < 2) return false;
+    return mode == MODE_OCC || mode == (MODE_MASK | MODE_OCC) ? strip_ok(o, mode, &lay) : false;
+}
+
+int obg::run_pixels_list(const obg_geom *g, int mode, const FrameLists &l, int32_t n_frames, const uint32_t *leaf,
+                    hipStream_t stream) {
+    Geo o{};
+    int rc = check_geom(g, &o, true);
+    if (rc != OBG_OK) return rc;
+    if (mode != MODE_OCC && mode != (MODE_MASK | MODE_OCC)) return fail(OBG_EINVAL, "internal: frame-list mode");
+    if (o.reg_cols < 2) return fail(OBG_EINVAL, "internal: frame lists need several regions per row");
+    if (n_frames < 1 || !l.rgb || !l.occ || ((mode & MODE_MASK) && (!l.mask || !leaf)))
+        return fail(OBG_EINVAL, "internal: frame lists");
+    return run_pixels(o, mode, nullptr, n_frames, leaf, nullptr, nullptr, nullptr, stream, &l);
+}
 
 extern "C" {
 

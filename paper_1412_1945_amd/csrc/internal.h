@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/obg.h"
 #include "device.h"
 
 namespace obg {
@@ -39,6 +40,12 @@ struct StripArgs {
     int32_t mask_row_words;
     uint32_t *occ;            // [n_frames][n_regions][words], zeroed and OR-ed into (or stored)
     uint32_t *counts;         // [n_frames][n_regions][8^d], zeroed, added into
+    // frame lists (device arrays, or all NULL): frame f's pixels, mask and
+    // trees start at rgb_list[f], mask_list[f], occ_list[f] instead of at
+    // fixed pitches from rgb, mask and occ
+    const uint8_t *const *rgb_list;
+    uint64_t *const *mask_list;
+    uint32_t *const *occ_list;
 };
 
 // Per-pixel fallback for any depth 1..8 and any region size.
@@ -96,5 +103,21 @@ hipError_t launch_score(const uint64_t *mask, const uint64_t *truth, int64_t row
 hipError_t launch_generic(int mode, const GenericArgs &a, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &a, hipStream_t stream);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t stream);
+
+// Frames of one geometry anywhere in device memory (the serving runtime's
+// arena blocks): mode MODE_OCC builds each frame's trees, MODE_MASK |
+// MODE_OCC also classifies against `leaf`.  The three arrays are device
+// arrays of n_frames pointers (mask_list unused without MODE_MASK); each
+// frame's trees are written whole (n_regions * words words).  Geometries
+// with several regions per row of regions that the LDS kernels take are
+// served this way (pixels_list_ok); others are refused.
+struct FrameLists {
+    const uint8_t *const *rgb;
+    uint64_t *const *mask;
+    uint32_t *const *occ;
+};
+bool pixels_list_ok(const obg_geom *g, int mode);
+int run_pixels_list(const obg_geom *g, int mode, const FrameLists &l, int32_t n_frames, const uint32_t *leaf,
+                    hipStream_t stream);
 
 }  // namespace obg

@@ -25,7 +25,15 @@
 
 namespace obg {
 
-template <int D, int MODE, int BLOCK, int PAD, bool REGION>
+// Trees of frame f: from the frame list, or at a fixed pitch.
+template <bool LIST>
+__device__ __forceinline__ uint32_t *frame_occ(const StripArgs &a, int f, int kw) {
+    return LIST ? a.occ_list[f] : a.occ + (int64_t)f * a.n_regions * kw;
+}
+
+// LIST: frames, masks and trees through the per-frame pointer arrays (a
+// separate instance, so the other kernels keep their registers)
+template <int D, int MODE, int BLOCK, int PAD, bool REGION, bool LIST = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
     (MODE == MODE_MASK && D == 5) ? 8 : ((MODE == (MODE_MASK | MODE_OCC) && BLOCK == 512) ? 4 : 1)))) void
 strip_kernel(StripArgs a) {
@@ -89,8 +97,7 @@ strip_kernel(StripArgs a) {
         const bool new_seg = (s != cur_s) || (f != cur_f);
         if (OCC && new_seg && cur_f >= 0) {
             __syncthreads();
-            occ_from_lds<D, PAD>(occ_lds, a.occ + ((int64_t)cur_f * a.n_regions + cur_reg0) * KW, cur_tiles, tid,
-                                 BLOCK, store);
+            occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store);
         }
         if (MASK && s != cur_s) {
             __syncthreads();
@@ -112,19 +119,19 @@ strip_kernel(StripArgs a) {
         const int gb = t * a.span;
         const int ge = min(gb + a.span, gcount);
         const int64_t strip_off = (int64_t)row0 * a.row_pitch;
-        const __amdgpu_buffer_rsrc_t rs =
-            make_rsrc(a.rgb + (int64_t)f * a.frame_pitch + strip_off, (uint32_t)(a.frame_pitch - strip_off));
+        const uint8_t *frame = LIST ? a.rgb_list[f] : a.rgb + (int64_t)f * a.frame_pitch;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(frame + strip_off, (uint32_t)(a.frame_pitch - strip_off));
         __amdgpu_buffer_rsrc_t ms = make_rsrc(nullptr, 0);
-        if (MASK)
-            ms = make_rsrc(a.mask + ((int64_t)f * a.height + row0) * a.mask_row_words,
-                           (uint32_t)rows * (uint32_t)a.mask_row_words * 8u);
+        if (MASK) {
+            uint64_t *fm = LIST ? a.mask_list[f] : a.mask + (int64_t)f * a.height * a.mask_row_words;
+            ms = make_rsrc(fm + (int64_t)row0 * a.mask_row_words, (uint32_t)rows * (uint32_t)a.mask_row_words * 8u);
+        }
         uint32_t *cbase = CNT ? a.counts + ((int64_t)f * a.n_regions + reg0) * LC : nullptr;
         span_loop<D, MODE, PAD, REGION, BLOCK>(a, rs, ms, gb, ge, leaf_lds, occ_lds, cbase, stage, ch);
     }
     if (OCC && cur_f >= 0) {
         __syncthreads();
-        occ_from_lds<D, PAD>(occ_lds, a.occ + ((int64_t)cur_f * a.n_regions + cur_reg0) * KW, cur_tiles, tid,
-                             BLOCK, store);
+        occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store);
     }
 }
 
@@ -291,6 +298,24 @@ static hipError_t allow_lds(K kernel, size_t lds) {
 template <int D, int LAY, bool REGION>
 static hipError_t launch_variant(int mode, int block, const StripArgs &a, int grid, size_t lds,
                                  hipStream_t st) {
+    if (a.rgb_list) {
+        // frame lists: region passes that build occupancy
+        if (!REGION || !a.occ_list || (mode != MODE_OCC && mode != (MODE_MASK | MODE_OCC)))
+            return hipErrorInvalidValue;
+        if (mode == MODE_OCC) {
+            if (block == 1024)
+                OBG_LAUNCH((strip_kernel<D, MODE_OCC, 1024, LAY, true, true>), 1024);
+            else
+                OBG_LAUNCH((strip_kernel<D, MODE_OCC, 256, LAY, true, true>), 256);
+        } else {
+            if (!a.mask_list) return hipErrorInvalidValue;
+            if (block == 512)
+                OBG_LAUNCH((strip_kernel<D, MODE_MASK | MODE_OCC, 512, LAY, true, true>), 512);
+            else
+                OBG_LAUNCH((strip_kernel<D, MODE_MASK | MODE_OCC, 256, LAY, true, true>), 256);
+        }
+        return hipGetLastError();
+    }
     switch (mode) {
         case MODE_MASK:
             if (block == 512)
@@ -340,9 +365,10 @@ size_t strip_lds_bytes(int depth, int mode, int reg_cols, int lay) {
 // Every pointer a mode writes or reads must be set; a launch with a missing
 // one is refused instead of faulting on the device.
 static bool strip_pointers_ok(int mode, const StripArgs &a) {
-    if (!a.rgb) return false;
-    if ((mode & MODE_MASK) && (!a.leaf || !a.mask)) return false;
-    if ((mode & MODE_OCC) && !a.occ) return false;
+    if (!a.rgb && !a.rgb_list) return false;
+    if ((mode & MODE_MASK) && (!a.leaf || (!a.mask && !a.mask_list))) return false;
+    if ((mode & MODE_OCC) && !a.occ && !a.occ_list) return false;
+    if ((a.rgb_list || a.occ_list || a.mask_list) && (mode & MODE_COUNTS)) return false;
     if ((mode & MODE_COUNTS) && !a.counts) return false;
     return true;
 }

@@ -189,6 +189,8 @@ struct Slot {
     int n_train_plain = 0;         // order: plain training, plain test, region test, region training
     ServeFrameDev *h_frames = nullptr, *d_frames = nullptr;
     MergeJobDev *h_jobs = nullptr, *d_jobs = nullptr;
+    // frame lists of the region frames: pixels, masks, ring slots (maxf each)
+    void **h_lists = nullptr, **d_lists = nullptr;
     obg_ingest_item *items = nullptr;
     unsigned long long *h_sum = nullptr, *d_sum = nullptr;
 };
@@ -320,7 +322,9 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             hipHostMalloc((void **)&sl.h_jobs, sizeof(MergeJobDev) * ns, hipHostMallocDefault) != hipSuccess ||
             hipMalloc((void **)&sl.d_jobs, sizeof(MergeJobDev) * ns) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_sum, sizeof(unsigned long long) * maxf, hipHostMallocDefault) != hipSuccess ||
-            hipMalloc((void **)&sl.d_sum, sizeof(unsigned long long) * maxf) != hipSuccess) {
+            hipMalloc((void **)&sl.d_sum, sizeof(unsigned long long) * maxf) != hipSuccess ||
+            hipHostMalloc((void **)&sl.h_lists, sizeof(void *) * 3 * maxf, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&sl.d_lists, sizeof(void *) * 3 * maxf) != hipSuccess) {
             rc = sfail(OBG_ENOMEM, "slot allocation failed");
             break;
         }
@@ -448,6 +452,11 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 sl.items[p].stream = fr.stream;
                 sl.items[p].frame = fr.frame;
                 sl.items[p].dst = fr.rgb;
+                if (p >= n_plain) {
+                    sl.h_lists[p - n_plain] = fr.rgb;
+                    sl.h_lists[maxf + p - n_plain] = fr.mask;
+                    sl.h_lists[2 * maxf + p - n_plain] = fd.occ;
+                }
             }
             // merges of plain streams in one launch; region streams merge alone
             int n_jobs = 0;
@@ -461,6 +470,9 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             if (ok) ok = hipMemcpyAsync(sl.d_frames, sl.h_frames, sizeof(ServeFrameDev) * n, hipMemcpyHostToDevice, st) == hipSuccess;
             if (ok && n_jobs)
                 ok = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, sizeof(MergeJobDev) * n_jobs, hipMemcpyHostToDevice, st) == hipSuccess;
+            if (ok && n > n_plain)
+                ok = hipMemcpyAsync(sl.d_lists, sl.h_lists, sizeof(void *) * 3 * maxf, hipMemcpyHostToDevice, st) ==
+                     hipSuccess;
             if (ok) ok = cfg->ingest(cfg->ingest_ctx, sl.items, n, st) == 0;
             if (ok) ok = hipEventRecord(sl.k0, st) == hipSuccess;
             if (ok) {
@@ -477,15 +489,33 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                     ServeArgs b{sl.d_frames, n_plain, n_groups, chunk};
                     hipLaunchKernelGGL(serve_kernel, dim3((unsigned)grid), dim3(kServeBlock), 0, st, b);
                 }
-                // frames with regions: the one-stream passes, tree into the ring slot
-                for (int p = n_plain; ok && p < n; ++p) {
-                    const SchedFrame &fr = F[sl.order[p]];
-                    const StreamDev &sd = D[fr.stream];
-                    uint32_t *slot = reinterpret_cast<uint32_t *>(sched.S[fr.stream].ring) +
-                                     (int64_t)fr.slot * sd.words * sd.n_regions;
-                    const uint32_t *leaf = reinterpret_cast<const uint32_t *>(sched.S[fr.stream].leaf);
-                    ok = (fr.test ? obg_classify(&sd.geom, fr.rgb, 1, leaf, fr.mask, slot, st)
-                                  : obg_train_frame(&sd.geom, fr.rgb, 1, slot, nullptr, st)) == OBG_OK;
+                // frames with regions: one pass per run of a stream's test
+                // (or training) frames over their frame lists, trees into the
+                // ring slots; geometries the LDS kernels do not take go one
+                // frame at a time through the one-stream entry points
+                for (int p = n_plain; ok && p < n;) {
+                    const SchedFrame &f0 = F[sl.order[p]];
+                    int q = p + 1;
+                    while (q < n && F[sl.order[q]].stream == f0.stream && F[sl.order[q]].test == f0.test) ++q;
+                    const StreamDev &sd = D[f0.stream];
+                    const uint32_t *leaf = reinterpret_cast<const uint32_t *>(sched.S[f0.stream].leaf);
+                    const int mode = f0.test ? (MODE_MASK | MODE_OCC) : MODE_OCC;
+                    if (pixels_list_ok(&sd.geom, mode)) {
+                        const int i0 = p - n_plain;
+                        FrameLists fl{reinterpret_cast<const uint8_t *const *>(sl.d_lists + i0),
+                                      reinterpret_cast<uint64_t *const *>(sl.d_lists + maxf + i0),
+                                      reinterpret_cast<uint32_t *const *>(sl.d_lists + 2 * maxf + i0)};
+                        ok = run_pixels_list(&sd.geom, mode, fl, q - p, leaf, st) == OBG_OK;
+                    } else {
+                        for (int r = p; ok && r < q; ++r) {
+                            const SchedFrame &fr = F[sl.order[r]];
+                            uint32_t *slot = reinterpret_cast<uint32_t *>(sched.S[fr.stream].ring) +
+                                             (int64_t)fr.slot * sd.words * sd.n_regions;
+                            ok = (fr.test ? obg_classify(&sd.geom, fr.rgb, 1, leaf, fr.mask, slot, st)
+                                          : obg_train_frame(&sd.geom, fr.rgb, 1, slot, nullptr, st)) == OBG_OK;
+                        }
+                    }
+                    p = q;
                 }
                 if (ok && n_jobs) {
                     int maxw = 1;
@@ -595,6 +625,8 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         if (sl.d_jobs) (void)hipFree(sl.d_jobs);
         if (sl.h_sum) (void)hipHostFree(sl.h_sum);
         if (sl.d_sum) (void)hipFree(sl.d_sum);
+        if (sl.h_lists) (void)hipHostFree(sl.h_lists);
+        if (sl.d_lists) (void)hipFree(sl.d_lists);
         delete[] sl.items;
     }
     if (t0) (void)hipEventDestroy(t0);

@@ -24,10 +24,12 @@ def env(oracle_lib):
 def _setup():
     from synth.frames import StreamSpec
     from synth.fast import poisson_arrivals
-    # the last two streams have one tree per region (Sections 3 and 4)
+    # the last four streams have one tree per region (Sections 3 and 4): one
+    # on the per-pixel fallback (24-pixel regions), two whose rows of regions
+    # are cut into chunks of region columns (the last one ragged)
     shapes = [(64, 32, 3, 5, (1, 2), 0, 0), (96, 40, 4, 6, (3, 10), 0, 0), (160, 24, 5, 4, (7, 10), 0, 0),
               (33, 17, 6, 7, (1, 2), 0, 0), (128, 64, 5, 8, (1, 1), 0, 0), (96, 64, 4, 6, (1, 2), 32, 32),
-              (70, 20, 3, 5, (3, 10), 24, 8)]
+              (70, 20, 3, 5, (3, 10), 24, 8), (320, 64, 4, 6, (1, 2), 32, 32), (400, 48, 5, 5, (1, 2), 48, 16)]
     specs, streams = [], []
     for i, (W, H, d, T, thr, rw, rh) in enumerate(shapes):
         specs.append(StreamSpec(W, H, T, 400, seed=21, stream=i, fg="ellipses", fg_coverage=0.15,
@@ -112,7 +114,7 @@ def test_serve_matches_oracle_and_alone(env):
     assert stats["merges"] == want
     assert stats["batches"] > 1
     _check_oracle(O, specs, streams, arrivals, masks)
-    for w in (0, 2, 4, 5):
+    for w in (0, 2, 4, 5, 7):
         print(f"[case] serve stream {w} alone", flush=True)
         _, alone, _ = _serve(obg, specs, streams, arrivals, [w])
         n = len(arrivals[w])
@@ -131,7 +133,9 @@ def test_serve_tight_budget_same_results(env):
     # rings and leaf sets of all streams, plus room for one frame of the
     # largest stream; every arrival is offered at once
     state = _state_bytes(streams)
-    frame = ((64 * 384 + 255) // 256) * 256 + 1024      # largest frame and its mask
+    rnd = lambda b: (b + 255) // 256 * 256                 # arena blocks are whole 256-byte units
+    frame = max(rnd((3 * s["width"] + 15) // 16 * 16 * s["height"]) + rnd(s["height"] * -(-s["width"] // 64) * 8)
+                for s in streams)                          # largest frame and its mask
     print(f"[case] serve with budget {state + frame}", flush=True)
     stats, sums, masks = _serve(obg, specs, streams, arrivals, every, budget=state + frame, speed=1000.0,
                                 watch=every)
