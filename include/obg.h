@@ -254,9 +254,13 @@ void obg_batch_destroy(obg_batch *batch);
  * to host buffers (watch_masks[w], [watch_max_frames][height][ceil(width/64)]).
  * Streams: depth 1..6, one tree per frame or per region (Sections 3 and 4);
  * pixels are packed RGB8 with row pitch 3*width rounded up to 16 bytes.
- * Frames of streams without regions go through one launch per batch; frames
- * of streams with regions take the one-stream passes (obg_train_frame,
- * obg_classify with occ_out, obg_merge) on the batch's HIP stream.
+ * Frames of streams without regions go through one launch per batch.  For a
+ * stream with regions, each run of its test (or training) frames in a batch
+ * is one pass of the region kernels over per-frame pointer lists (the same
+ * results as obg_classify with occ_out, or obg_train_frame, frame by frame),
+ * on the batch's HIP stream; geometries only the per-pixel kernel takes go
+ * frame by frame through those entry points.  Their merges are obg_merge
+ * calls.
  * Admission: a frame takes one arena block (its pixels, and for a test frame
  * its mask).  When a frame does not fit, its stream goes first and no other
  * frame is admitted until it does, so no stream starves; a frame that cannot
