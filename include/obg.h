@@ -341,7 +341,9 @@ int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
  *                               occupancy (default 2 at 1024 threads, else 4)
  *   OBG_TUNE_CLASSIFY_WG_PER_CU workgroups per CU of classify-only passes
  *                               (default 2, fewer if LDS does not allow)
- *   OBG_TUNE_CLASSIFY_SPAN      16-pixel groups per work item (default 512)
+ *   OBG_TUNE_CLASSIFY_SPAN      16-pixel groups per work item of classify-only
+ *                               passes (default 832; 1024 with compact
+ *                               tables: d = 6 and most region tables)
  *   OBG_TUNE_CLASSIFY_BLOCK     threads per workgroup of classify passes:
  *                               256 or 512 (default; 256 for fused region
  *                               work items of fewer than 2048 groups)

@@ -303,12 +303,14 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
             }
         }
     } else {
-        // measured on the 1080p stream: two 512-thread groups per CU streaming
-        // 512-group items round-robin give the highest read+write rate
+        // measured on 1000 frames of the 1080p stream: two 512-thread groups
+        // per CU streaming items round-robin give the highest read+write
+        // rate; items of 832 groups beat 512 by 3-11 % at d = 3..5 (5.41-5.51
+        // vs 4.95-5.23 TB/s), and compact tables (d = 6, regions) prefer 1024
         int want = tune(OBG_TUNE_CLASSIFY_WG_PER_CU, 2);
         if (want > per_cu) want = per_cu;
         target = (int64_t)cus * want;
-        const int64_t span_groups = tune(OBG_TUNE_CLASSIFY_SPAN, 512);
+        const int64_t span_groups = tune(OBG_TUNE_CLASSIFY_SPAN, lay == LAY_COMPACT ? 1024 : 832);
         spans = (groups_strip + span_groups - 1) / span_groups;
     }
     // spans are whole multiples of 4 groups (one 64-pixel mask word)

@@ -350,7 +350,7 @@ int autotune(obg_batch *b, hipStream_t st) {
     b->tune_default_ms = best_ms;
     Shape best = base;
     int n = 0;
-    const int cblocks[] = {256, 512}, cwpcs[] = {1, 2, 4}, cspans[] = {256, 512, 1024, 4096};
+    const int cblocks[] = {256, 512}, cwpcs[] = {1, 2, 4}, cspans[] = {256, 512, 832, 1024, 4096};
     const int tblocks[] = {256, 1024}, twpcs[] = {1, 2, 4}, titems[] = {1, 4};
     for (int cb : cblocks)
         for (int cw : cwpcs)
@@ -481,7 +481,7 @@ int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t
     hipError_t e = hipMalloc(&b->d, sizeof(BatchStreamDev) * n_streams);
     if (e == hipSuccess) e = hipMalloc(&b->d_sum, sizeof(unsigned long long));
     if (e != hipSuccess) { destroy(b); return bfail(OBG_ENOMEM, "descriptor allocation: %s", hipGetErrorString(e)); }
-    b->shape = Shape{1024, 2, 1, 512, 2, 512};
+    b->shape = Shape{1024, 2, 1, 512, 2, 832};
     int rc = plan_items(b);
     if (rc == OBG_OK && (flags & OBG_BATCH_AUTOTUNE)) rc = autotune(b, stream);
     if (rc == OBG_OK && !(flags & OBG_BATCH_NO_GRAPH)) {

@@ -53,7 +53,7 @@ extern "C" int obg_probe(int kind, const void *src, void *dst, int64_t bytes, ui
     }
     if (kind != OBG_PROBE_READ && kind != OBG_PROBE_READ_WRITE) return OBG_EINVAL;
     if (!sink || grid < 1 || grid > 65536) return OBG_EINVAL;
-    const int span = 512;
+    const int span = 832;   // groups per item: the classify default
     const int64_t n_items = bytes / (48 * (int64_t)span);
     if (n_items < 1) return OBG_EINVAL;
     if (kind == OBG_PROBE_READ_WRITE) {
