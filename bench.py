@@ -123,9 +123,10 @@ def host_cpu():
 def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, budget_s):
     """The oracle as it is, single-threaded: trees of every training frame, the
     merge, then test frames (fetched one at a time) until `budget_s` seconds
-    have passed or `n_test` frames are classified.  A second leg classifies up
-    to 8 frames per host thread with the same model on all the host's threads
-    (the oracle's C calls release the GIL); it is reported beside the
+    have passed or `n_test` frames are classified.  Two more legs use all the
+    host's threads (the oracle's C calls release the GIL): up to 8 test frames
+    per thread classified with the same model, and the training frames' trees
+    built with the frames dealt to the threads.  They are reported beside the
     single-threaded figure."""
     from oracle import octree
     t0 = time.perf_counter()
@@ -159,9 +160,26 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
             t1 = time.perf_counter()
             list(ex.map(model.classify, frames))
             t_mt = time.perf_counter() - t1
-        out["threaded_classify"] = {"threads": threads, "frames": len(frames),
-                                    "seconds": round(t_mt, 3),
-                                    "gpixel_s": round(len(frames) * spec.pixels / t_mt / 1e9, 5)}
+            out["threaded_classify"] = {"threads": threads, "frames": len(frames),
+                                        "seconds": round(t_mt, 3),
+                                        "gpixel_s": round(len(frames) * spec.pixels / t_mt / 1e9, 5)}
+            # the training frames' trees, the frames dealt to the threads, each
+            # thread building into a forest of its own (the merge needs them in
+            # one forest and stays single-threaded)
+            parts = [host_train[i::threads] for i in range(threads) if host_train[i::threads]]
+
+            def build(part):
+                forest = octree.Forest(spec.width, spec.height, depth, region[0], region[1])
+                forest.add_frames(part)
+                return forest
+
+            t1 = time.perf_counter()
+            forests = list(ex.map(build, parts))
+            t_mt = time.perf_counter() - t1
+            del forests
+            out["threaded_trees"] = {"threads": len(parts), "frames": len(host_train),
+                                     "seconds": round(t_mt, 3),
+                                     "gpixel_s": round(len(host_train) * spec.pixels / t_mt / 1e9, 5)}
     return out
 
 
