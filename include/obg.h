@@ -175,8 +175,11 @@ int obg_score(const obg_geom *g, const uint64_t *mask, const uint64_t *truth, in
  * three steps, each ONE persistent launch over all streams: the per-frame
  * trees of every training frame (Algorithm 1 + Section 2 pruning), the merge
  * of every stream's trees with its own threshold (Algorithm 2), and the
- * foreground masks of every test frame (Algorithm 3).  The steps are captured
- * once in a HIP graph at creation and replayed.  Outputs are byte-identical
+ * foreground masks of every test frame (Algorithm 3).  The autotuner may
+ * instead split the trees and masks steps into one persistent launch per
+ * depth present (all streams of that depth; the code of one depth inlined),
+ * when that is faster.  The steps are captured once in a HIP graph at
+ * creation and replayed.  Outputs are byte-identical
  * to the one-stream calls (obg_train_frame / obg_merge / obg_classify).
  *
  * Each stream: plain geometry (region_w = region_h = 0), depth 1..6,
@@ -219,6 +222,8 @@ typedef struct obg_batch_info {
     int32_t graph;                            /* 1: runs replay a graph    */
     int32_t tune_candidates;                  /* shapes timed (autotune)   */
     double tune_default_ms, tune_best_ms;     /* one run, default vs chosen */
+    int32_t classify_round_robin;             /* 1: classify items dealt round-robin */
+    int32_t per_depth_launches;               /* 1: one launch per depth and phase */
 } obg_batch_info;
 
 int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t flags,

@@ -67,11 +67,10 @@ __device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it) {
     return lo;
 }
 
-// One call per (depth, order): each depth's code gets its own register
-// allocation instead of the kernel taking the largest of all six inlined.
+// Work item `local` of stream sd: the frame and the groups it covers.
 template <int D, int LAY, int MODE, int BLOCK>
-__device__ __attribute__((noinline)) void batch_item(const BatchArgs &b, const BatchStreamDev &sd, int64_t local,
-                                           uint32_t *tab, uint16_t *st_mask, bool new_stream) {
+__device__ __forceinline__ void item_body(const BatchArgs &b, const BatchStreamDev &sd, int64_t local,
+                                          uint32_t *tab, uint16_t *st_mask, bool new_stream) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr int LW = lds_words(D, LAY);
@@ -103,6 +102,44 @@ __device__ __attribute__((noinline)) void batch_item(const BatchArgs &b, const B
     if (OCC) {
         __syncthreads();
         occ_from_lds<D, LAY>(tab, sd.occ + (int64_t)f * sd.words, 1, tid, BLOCK);
+    }
+}
+
+// One call per (depth, order) in the one-launch kernel: each depth's code
+// gets its own register allocation (all six inlined take 187 VGPRs, two
+// waves per SIMD); the price is a call per item that saves 12 VGPRs to the
+// stack.
+template <int D, int LAY, int MODE, int BLOCK>
+__device__ __attribute__((noinline)) void batch_item(const BatchArgs &b, const BatchStreamDev &sd, int64_t local,
+                                           uint32_t *tab, uint16_t *st_mask, bool new_stream) {
+    item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, new_stream);
+}
+
+// The streams of one depth (b.streams points at the first of them, items
+// numbered from 0 over them): the item code inlined, the LDS table sized for
+// the depth.
+template <int D, int LAY, int MODE, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void batch_depth_kernel(BatchArgs b) {
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    __shared__ uint32_t tab[lds_words(D, LAY)];
+    __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
+    int64_t i0, i1, istep;
+    if (b.interleave) {
+        i0 = blockIdx.x;
+        i1 = b.n_items;
+        istep = gridDim.x;
+    } else {
+        i0 = b.n_items * blockIdx.x / gridDim.x;
+        i1 = b.n_items * (blockIdx.x + 1) / gridDim.x;
+        istep = 1;
+    }
+    int cur = -1;
+    for (int64_t it = i0; it < i1; it += istep) {
+        const int s = stream_of<MODE>(b, it);
+        const BatchStreamDev &sd = b.streams[s];
+        const int64_t local = it - (MASK ? sd.citem0 : sd.titem0);
+        item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, s != cur);
+        cur = s;
     }
 }
 
@@ -189,6 +226,14 @@ int bfail(int code, const char *fmt, ...) {
 struct Shape {
     int train_block, train_wpc, train_items_per_wg;
     int classify_block, classify_wpc, classify_span;
+    int classify_rr;          // 1: classify items dealt round-robin, 0: contiguous runs
+    int per_depth;            // 1: one launch per depth and phase, 0: one launch per phase
+};
+
+// Streams of one depth: [s0, s1) of the (depth-sorted) descriptors.
+struct DepthGroup {
+    int depth, s0, s1;
+    int64_t train_items, classify_items;   // with per-depth launches
 };
 
 }  // namespace
@@ -198,7 +243,8 @@ struct obg_batch {
     int n_streams = 0;
     int cus = 256;
     std::vector<obg_stream_desc> desc;
-    std::vector<BatchStreamDev> h;
+    std::vector<BatchStreamDev> h;        // sorted by depth
+    std::vector<DepthGroup> groups;
     BatchStreamDev *d = nullptr;
     unsigned long long *d_sum = nullptr;
     int64_t train_items = 0, classify_items = 0;
@@ -225,24 +271,76 @@ int plan_items(obg_batch *b) {
     // when they are small enough (one LDS flush per item)
     int64_t tspan_target = tgroups / std::max<int64_t>(1, train_wgs * b->shape.train_items_per_wg);
     tspan_target = std::max<int64_t>(tspan_target, 4096);
-    int64_t t0 = 0, c0 = 0;
-    for (auto &h : b->h) {
-        int64_t ts = (std::min<int64_t>(tspan_target, h.groups) + 3) & ~int64_t(3);
-        h.tspans = (int32_t)((h.groups + ts - 1) / ts);
-        h.tspan = (int32_t)((((h.groups + h.tspans - 1) / h.tspans) + 3) & ~3);
-        int64_t cs = (std::min<int64_t>(b->shape.classify_span, h.groups) + 3) & ~int64_t(3);
-        h.cspans = (int32_t)((h.groups + cs - 1) / cs);
-        h.cspan = (int32_t)((((h.groups + h.cspans - 1) / h.cspans) + 3) & ~3);
-        h.titem0 = t0;
-        h.citem0 = c0;
-        t0 += (int64_t)h.tspans * h.n_train;
-        c0 += (int64_t)h.cspans * h.n_test;
+    // item numbers run over all streams (one launch per phase) or restart at
+    // each depth group (one launch per depth)
+    int64_t t0 = 0, c0 = 0, tt = 0, ct = 0;
+    for (auto &gr : b->groups) {
+        if (b->shape.per_depth) t0 = c0 = 0;
+        const int64_t gt = t0, gc = c0;
+        for (int s = gr.s0; s < gr.s1; ++s) {
+            BatchStreamDev &h = b->h[s];
+            int64_t ts = (std::min<int64_t>(tspan_target, h.groups) + 3) & ~int64_t(3);
+            h.tspans = (int32_t)((h.groups + ts - 1) / ts);
+            h.tspan = (int32_t)((((h.groups + h.tspans - 1) / h.tspans) + 3) & ~3);
+            int64_t cs = (std::min<int64_t>(b->shape.classify_span, h.groups) + 3) & ~int64_t(3);
+            h.cspans = (int32_t)((h.groups + cs - 1) / cs);
+            h.cspan = (int32_t)((((h.groups + h.cspans - 1) / h.cspans) + 3) & ~3);
+            h.titem0 = t0;
+            h.citem0 = c0;
+            t0 += (int64_t)h.tspans * h.n_train;
+            c0 += (int64_t)h.cspans * h.n_test;
+        }
+        gr.train_items = t0 - gt;
+        gr.classify_items = c0 - gc;
+        tt += gr.train_items;
+        ct += gr.classify_items;
     }
-    b->train_items = t0;
-    b->classify_items = c0;
+    b->train_items = tt;
+    b->classify_items = ct;
     hipError_t e = hipMemcpy(b->d, b->h.data(), sizeof(BatchStreamDev) * b->h.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bfail(OBG_EHIP, "descriptor upload: %s", hipGetErrorString(e));
     return OBG_OK;
+}
+
+template <int D, int LAY>
+hipError_t launch_depth(obg_batch *b, const DepthGroup &gr, bool train, hipStream_t st) {
+    const Shape &sh = b->shape;
+    const BatchStreamDev *d = b->d + gr.s0;
+    const int n = gr.s1 - gr.s0;
+    if (train) {
+        BatchArgs a{d, n, gr.train_items, 0, 0};
+        const int grid = (int)std::min<int64_t>(gr.train_items, (int64_t)b->cus * sh.train_wpc);
+        if (sh.train_block == 1024)
+            hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_OCC, 1024>), dim3(grid), dim3(1024), 0, st, a);
+        else
+            hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_OCC, 256>), dim3(grid), dim3(256), 0, st, a);
+    } else {
+        BatchArgs a{d, n, gr.classify_items, sh.classify_rr, sh.classify_span <= kStageGroups ? 1 : 0};
+        const int grid = (int)std::min<int64_t>(gr.classify_items, (int64_t)b->cus * sh.classify_wpc);
+        if (sh.classify_block == 512)
+            hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_MASK, 512>), dim3(grid), dim3(512), 0, st, a);
+        else
+            hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_MASK, 256>), dim3(grid), dim3(256), 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+// One launch per depth group of the phase (train or classify).
+hipError_t enqueue_depths(obg_batch *b, bool train, hipStream_t st) {
+    for (const DepthGroup &gr : b->groups) {
+        if ((train ? gr.train_items : gr.classify_items) <= 0) continue;
+        hipError_t e;
+        switch (gr.depth) {
+            case 1: e = launch_depth<1, LAY_WIDE>(b, gr, train, st); break;
+            case 2: e = launch_depth<2, LAY_WIDE>(b, gr, train, st); break;
+            case 3: e = launch_depth<3, LAY_WIDE>(b, gr, train, st); break;
+            case 4: e = launch_depth<4, LAY_WIDE>(b, gr, train, st); break;
+            case 5: e = launch_depth<5, LAY_WIDE>(b, gr, train, st); break;
+            default: e = launch_depth<6, LAY_COMPACT>(b, gr, train, st); break;
+        }
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t enqueue(obg_batch *b, hipStream_t st) {
@@ -250,6 +348,13 @@ hipError_t enqueue(obg_batch *b, hipStream_t st) {
     hipLaunchKernelGGL(batch_zero_kernel, dim3(64, ny), dim3(256), 0, st, (const BatchStreamDev *)b->d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (b->shape.per_depth) {
+        if ((e = enqueue_depths(b, true, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(batch_merge_kernel, dim3((b->max_words + 255) / 256, ny), dim3(256), 0, st,
+                           (const BatchStreamDev *)b->d);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        return enqueue_depths(b, false, st);
+    }
     if (b->train_items > 0) {
         BatchArgs a{b->d, ny, b->train_items, 0, 0};
         const int grid = (int)std::min<int64_t>(b->train_items, (int64_t)b->cus * b->shape.train_wpc);
@@ -263,8 +368,12 @@ hipError_t enqueue(obg_batch *b, hipStream_t st) {
                        (const BatchStreamDev *)b->d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (b->classify_items > 0) {
-        // contiguous runs: a workgroup meets each stream's leaf table once
-        BatchArgs a{b->d, ny, b->classify_items, 0, b->shape.classify_span <= kStageGroups ? 1 : 0};
+        // round-robin: the items in flight at any moment are neighbours in
+        // memory, and items are numbered stream by stream, so a workgroup
+        // reloads a leaf table only where its items cross into the next
+        // stream; contiguous runs meet each stream's table once
+        BatchArgs a{b->d, ny, b->classify_items, b->shape.classify_rr,
+                    b->shape.classify_span <= kStageGroups ? 1 : 0};
         const int grid = (int)std::min<int64_t>(b->classify_items, (int64_t)b->cus * b->shape.classify_wpc);
         if (b->shape.classify_block == 512)
             hipLaunchKernelGGL((batch_kernel<MODE_MASK, 512>), dim3(grid), dim3(512), 0, st, a);
@@ -350,23 +459,37 @@ int autotune(obg_batch *b, hipStream_t st) {
     b->tune_default_ms = best_ms;
     Shape best = base;
     int n = 0;
+    // one launch per phase or per depth and phase, with the default shape
+    {
+        Shape s = best;
+        s.per_depth = !base.per_depth;
+        b->shape = s;
+        float ms = 0;
+        if ((rc = time_shape(b, st, &ms))) return rc;
+        unsigned long long h = 0;
+        if ((rc = checksum(b, st, &h))) return rc;
+        if (h != ref) return bfail(OBG_EHIP, "autotune: shape gives different output (internal error)");
+        ++n;
+        if (ms < best_ms) { best_ms = ms; best = s; }
+    }
     const int cblocks[] = {256, 512}, cwpcs[] = {1, 2, 4}, cspans[] = {256, 512, 832, 1024, 4096};
     const int tblocks[] = {256, 1024}, twpcs[] = {1, 2, 4}, titems[] = {1, 4};
     for (int cb : cblocks)
         for (int cw : cwpcs)
-            for (int cs : cspans) {
-                Shape s = best;
-                s.classify_block = cb; s.classify_wpc = cw; s.classify_span = cs;
-                if (cb == 512 && cw > 2) continue;   // 32 waves per CU at most
-                b->shape = s;
-                float ms = 0;
-                if ((rc = time_shape(b, st, &ms))) return rc;
-                unsigned long long h = 0;
-                if ((rc = checksum(b, st, &h))) return rc;
-                if (h != ref) return bfail(OBG_EHIP, "autotune: shape gives different output (internal error)");
-                ++n;
-                if (ms < best_ms) { best_ms = ms; best = s; }
-            }
+            for (int cs : cspans)
+                for (int rr = 0; rr < 2; ++rr) {
+                    Shape s = best;
+                    s.classify_block = cb; s.classify_wpc = cw; s.classify_span = cs; s.classify_rr = rr;
+                    if (cb == 512 && cw > 2) continue;   // 32 waves per CU at most
+                    b->shape = s;
+                    float ms = 0;
+                    if ((rc = time_shape(b, st, &ms))) return rc;
+                    unsigned long long h = 0;
+                    if ((rc = checksum(b, st, &h))) return rc;
+                    if (h != ref) return bfail(OBG_EHIP, "autotune: shape gives different output (internal error)");
+                    ++n;
+                    if (ms < best_ms) { best_ms = ms; best = s; }
+                }
     for (int tb : tblocks)
         for (int tw : twpcs)
             for (int ti : titems) {
@@ -473,6 +596,15 @@ int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t
         b->px_test += (int64_t)g.width * g.height * sd.n_test;
         b->h.push_back(h);
     }
+    // descriptors sorted by depth (outputs are addressed through them, so the
+    // order is free): each depth's streams are one contiguous group
+    std::stable_sort(b->h.begin(), b->h.end(),
+                     [](const BatchStreamDev &x, const BatchStreamDev &y) { return x.depth < y.depth; });
+    for (int s = 0; s < n_streams; ++s) {
+        if (b->groups.empty() || b->groups.back().depth != b->h[s].depth)
+            b->groups.push_back(DepthGroup{b->h[s].depth, s, s, 0, 0});
+        b->groups.back().s1 = s + 1;
+    }
     // every descriptor is valid: only now touch the device
     if (hipGetDevice(&b->device) != hipSuccess) { destroy(b); return bfail(OBG_EHIP, "no device"); }
     int cus = 0;
@@ -481,7 +613,7 @@ int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t
     hipError_t e = hipMalloc(&b->d, sizeof(BatchStreamDev) * n_streams);
     if (e == hipSuccess) e = hipMalloc(&b->d_sum, sizeof(unsigned long long));
     if (e != hipSuccess) { destroy(b); return bfail(OBG_ENOMEM, "descriptor allocation: %s", hipGetErrorString(e)); }
-    b->shape = Shape{1024, 2, 1, 512, 2, 832};
+    b->shape = Shape{256, 4, 4, 512, 2, 832, 1, 0};
     int rc = plan_items(b);
     if (rc == OBG_OK && (flags & OBG_BATCH_AUTOTUNE)) rc = autotune(b, stream);
     if (rc == OBG_OK && !(flags & OBG_BATCH_NO_GRAPH)) {
@@ -517,6 +649,8 @@ int obg_batch_info_get(const obg_batch *b, obg_batch_info *out) {
     out->classify_block = b->shape.classify_block;
     out->classify_wg_per_cu = b->shape.classify_wpc;
     out->classify_span = b->shape.classify_span;
+    out->classify_round_robin = b->shape.classify_rr;
+    out->per_depth_launches = b->shape.per_depth;
     out->graph = b->use_graph ? 1 : 0;
     out->tune_candidates = b->tune_candidates;
     out->tune_default_ms = b->tune_default_ms;

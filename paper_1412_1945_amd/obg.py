@@ -56,6 +56,7 @@ class BatchInfo(ctypes.Structure):
         ("classify_span", ctypes.c_int32),
         ("graph", ctypes.c_int32), ("tune_candidates", ctypes.c_int32),
         ("tune_default_ms", ctypes.c_double), ("tune_best_ms", ctypes.c_double),
+        ("classify_round_robin", ctypes.c_int32), ("per_depth_launches", ctypes.c_int32),
     ]
 
 
