@@ -310,6 +310,16 @@ typedef struct obg_serve_config {
     int32_t n_watch;
     uint64_t *const *watch_masks;
     int32_t watch_max_frames;
+    /* Checkpoint, NULLABLE (host buffers of obg_serve_state_bytes bytes).
+       state_out receives, when the run ends, every stream's merged leaf set,
+       its ring of per-frame trees and the index of its next frame.  state_in
+       restores such a state (written for the same streams: geometry, depth,
+       n_train, regions, and the same remerge_window) before the first frame
+       is admitted; arrivals[s][i] is then frame next_frame[s] + i, and every
+       result of the resumed run equals that of one run over all the frames.
+       A state that does not match is refused with OBG_EINVAL. */
+    const void *state_in;
+    void *state_out;
 } obg_serve_config;
 
 typedef struct obg_serve_stats {
@@ -327,6 +337,11 @@ typedef struct obg_serve_stats {
 } obg_serve_stats;
 
 int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
+/* Bytes of a serving checkpoint of these streams (-1 if a description is
+   invalid): a 16-byte header (magic, n_streams, remerge_window), 48 bytes per
+   stream (geometry, ring length, next frame, tree bytes), then per stream its
+   leaf set and its ring of trees, each padded to 8 bytes. */
+int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams, int32_t remerge_window);
 
 /*
  * Launch-shape knobs of the pixel kernels, process-wide, for the autotuner

@@ -231,7 +231,59 @@ void merge_job(MergeJobDev &j, const StreamDev &sd, const uint32_t *ring, uint32
     while ((1 << j.planes) <= n) ++j.planes;
 }
 
+// Checkpoint layout: header, one record per stream, then per stream the leaf
+// set and the ring, each padded to 8 bytes.
+constexpr uint64_t kStateMagic = 0x3156524553474230ull;   // "0BGSERV1"
+struct StateHeader {
+    uint64_t magic;
+    int32_t n_streams, window;
+};
+struct StateStream {
+    int32_t width, height, depth, n_train, region_w, region_h, ring_len, pad;
+    int64_t next_frame;
+    uint64_t tree_bytes;
+};
+static_assert(sizeof(StateHeader) == 16 && sizeof(StateStream) == 48, "checkpoint layout");
+
+uint64_t pad8(uint64_t b) { return (b + 7) & ~uint64_t(7); }
+
+bool stream_ok(const obg_serve_stream &c) {
+    return c.width >= 1 && c.height >= 1 && c.depth >= 1 && c.depth <= 6 && c.n_train >= 1 && c.n_train <= 65535 &&
+           c.thr_num != 0 && c.thr_den != 0 && c.region_w >= 0 && c.region_h >= 0 &&
+           (c.region_w == 0) == (c.region_h == 0) && c.width <= (1 << 24) && c.height <= (1 << 24);
+}
+
+SchedStream sched_stream(const obg_serve_stream &c) {
+    const int nreg = c.region_w ? ((c.width + c.region_w - 1) / c.region_w) * ((c.height + c.region_h - 1) / c.region_h) : 1;
+    return SchedStream{c.width, c.height, c.depth, c.n_train, nreg};
+}
+
+StateStream state_record(const obg_serve_stream &c, int window, int64_t next_frame) {
+    StateStream r{};
+    r.width = c.width;
+    r.height = c.height;
+    r.depth = c.depth;
+    r.n_train = c.n_train;
+    r.region_w = c.region_w;
+    r.region_h = c.region_h;
+    r.ring_len = c.n_train > window ? c.n_train : window;
+    r.next_frame = next_frame;
+    r.tree_bytes = sched_tree_bytes(sched_stream(c));
+    return r;
+}
+
 }  // namespace
+
+extern "C" int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams, int32_t remerge_window) {
+    if (!streams || n_streams < 1 || remerge_window < 1) return -1;
+    uint64_t b = sizeof(StateHeader) + (uint64_t)n_streams * sizeof(StateStream);
+    for (int s = 0; s < n_streams; ++s) {
+        if (!stream_ok(streams[s])) return -1;
+        const StateStream r = state_record(streams[s], remerge_window, 0);
+        b += pad8(r.tree_bytes) + pad8((uint64_t)r.ring_len * r.tree_bytes);
+    }
+    return (int64_t)b;
+}
 
 extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats) {
     if (!cfg || !stats) return sfail(OBG_EINVAL, "config and stats must not be NULL");
@@ -293,11 +345,30 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             return sfail(OBG_EINVAL, "internal size mismatch");
     }
 
-    // arrivals in time order
+    // a restored state: every record must describe the same stream
+    std::vector<int64_t> first(ns, 0);
+    if (cfg->state_in) {
+        const uint8_t *p = static_cast<const uint8_t *>(cfg->state_in);
+        StateHeader h;
+        std::memcpy(&h, p, sizeof h);
+        if (h.magic != kStateMagic || h.n_streams != ns || h.window != cfg->remerge_window)
+            return sfail(OBG_EINVAL, "state_in: not a checkpoint of these streams (header)");
+        for (int s = 0; s < ns; ++s) {
+            StateStream r;
+            std::memcpy(&r, p + sizeof(StateHeader) + (uint64_t)s * sizeof(StateStream), sizeof r);
+            StateStream want = state_record(cfg->streams[s], cfg->remerge_window, r.next_frame);
+            if (std::memcmp(&r, &want, sizeof r) != 0 || r.next_frame < 0 ||
+                r.next_frame + cfg->n_arrivals[s] > (int64_t)0x7FFFFFFF)
+                return sfail(OBG_EINVAL, "state_in: stream record does not match the stream");
+            first[s] = r.next_frame;
+        }
+    }
+
+    // arrivals in time order (frame numbers continue from a restored state)
     struct Arr { double t; int s, f; };
     std::vector<Arr> arr;
     for (int s = 0; s < ns; ++s)
-        for (int f = 0; f < cfg->n_arrivals[s]; ++f) arr.push_back({cfg->arrivals[s][f], s, f});
+        for (int f = 0; f < cfg->n_arrivals[s]; ++f) arr.push_back({cfg->arrivals[s][f], s, (int)(first[s] + f)});
     std::stable_sort(arr.begin(), arr.end(), [](const Arr &x, const Arr &y) { return x.t < y.t; });
 
     uint8_t *arena_mem = nullptr;
@@ -309,6 +380,30 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                                    arena_mem, cfg->budget_bytes);
         if (src == -1) rc = sfail(OBG_EINVAL, "bad stream description");
         if (src == -2) rc = sfail(OBG_ENOMEM, "budget smaller than the streams' rings and leaf sets");
+    }
+    if (rc == OBG_OK && !cfg->state_in) {
+        // a fresh run starts from empty rings and leaf sets, so that a saved
+        // state holds the same bytes however the frames were batched
+        for (int s = 0; s < ns && rc == OBG_OK; ++s) {
+            const uint64_t tb = sched_tree_bytes(sc[s]);
+            if (hipMemset(sched.S[s].leaf, 0, tb) != hipSuccess ||
+                hipMemset(sched.S[s].ring, 0, (uint64_t)sched.S[s].ring_len * tb) != hipSuccess)
+                rc = sfail(OBG_EHIP, "clearing the rings failed");
+        }
+        if (rc == OBG_OK && hipDeviceSynchronize() != hipSuccess) rc = sfail(OBG_EHIP, "clearing the rings failed");
+    }
+    if (rc == OBG_OK && cfg->state_in) {
+        // leaf sets and rings into the arena
+        const uint8_t *p = static_cast<const uint8_t *>(cfg->state_in) + sizeof(StateHeader) +
+                           (uint64_t)ns * sizeof(StateStream);
+        for (int s = 0; s < ns && rc == OBG_OK; ++s) {
+            const StateStream r = state_record(cfg->streams[s], cfg->remerge_window, 0);
+            const uint64_t ring_b = (uint64_t)r.ring_len * r.tree_bytes;
+            if (hipMemcpy(sched.S[s].leaf, p, r.tree_bytes, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(sched.S[s].ring, p + pad8(r.tree_bytes), ring_b, hipMemcpyHostToDevice) != hipSuccess)
+                rc = sfail(OBG_EHIP, "state_in: copy to the device failed");
+            p += pad8(r.tree_bytes) + pad8(ring_b);
+        }
     }
     const int maxf = cfg->max_batch_frames;
     std::vector<Slot> slots(cfg->max_inflight);
@@ -448,7 +543,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 fd.pad_ = 0;
                 fd.g0 = n_groups;
                 n_groups += fd.groups;
-                sl.arrival[p] = cfg->arrivals[fr.stream][fr.frame] / cfg->speed;
+                sl.arrival[p] = cfg->arrivals[fr.stream][fr.frame - first[fr.stream]] / cfg->speed;
                 sl.items[p].stream = fr.stream;
                 sl.items[p].frame = fr.frame;
                 sl.items[p].dst = fr.rgb;
@@ -588,6 +683,23 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     const double wall = wall_now();
     for (auto &sl : slots)
         if (sl.st) (void)hipStreamSynchronize(sl.st);
+    if (rc == OBG_OK && cfg->state_out) {
+        // every batch has completed: the arena holds the final models and rings
+        uint8_t *p = static_cast<uint8_t *>(cfg->state_out);
+        const StateHeader h{kStateMagic, ns, cfg->remerge_window};
+        std::memcpy(p, &h, sizeof h);
+        uint8_t *data = p + sizeof(StateHeader) + (uint64_t)ns * sizeof(StateStream);
+        for (int s = 0; s < ns && rc == OBG_OK; ++s) {
+            const StateStream r = state_record(cfg->streams[s], cfg->remerge_window, first[s] + cfg->n_arrivals[s]);
+            std::memcpy(p + sizeof(StateHeader) + (uint64_t)s * sizeof(StateStream), &r, sizeof r);
+            const uint64_t ring_b = (uint64_t)r.ring_len * r.tree_bytes;
+            std::memset(data, 0, pad8(r.tree_bytes) + pad8(ring_b));
+            if (hipMemcpy(data, sched.S[s].leaf, r.tree_bytes, hipMemcpyDeviceToHost) != hipSuccess ||
+                hipMemcpy(data + pad8(r.tree_bytes), sched.S[s].ring, ring_b, hipMemcpyDeviceToHost) != hipSuccess)
+                rc = sfail(OBG_EHIP, "state_out: copy from the device failed");
+            data += pad8(r.tree_bytes) + pad8(ring_b);
+        }
+    }
     std::sort(lat.begin(), lat.end());
     auto pct = [&](double p) -> double {
         if (lat.empty()) return 0.0;

@@ -78,6 +78,7 @@ class ServeConfig(ctypes.Structure):
         ("checksums", ctypes.POINTER(ctypes.c_uint64)), ("checksum_stride", ctypes.c_int32),
         ("watch_streams", ctypes.POINTER(ctypes.c_int32)), ("n_watch", ctypes.c_int32),
         ("watch_masks", ctypes.POINTER(ctypes.POINTER(ctypes.c_uint64))), ("watch_max_frames", ctypes.c_int32),
+        ("state_in", ctypes.c_void_p), ("state_out", ctypes.c_void_p),
     ]
 
 
@@ -125,6 +126,7 @@ def load() -> ctypes.CDLL:
             "obg_batch_info_get": (ctypes.c_int, [P, ctypes.POINTER(BatchInfo)]),
             "obg_batch_destroy": (None, [P]),
             "obg_serve_run": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(ServeStats)]),
+            "obg_serve_state_bytes": (I64, [ctypes.POINTER(ServeStream), I32, I32]),
             "obg_last_error": (ctypes.c_char_p, []),
             "obg_version": (ctypes.c_char_p, []),
         }
@@ -140,7 +142,7 @@ def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
             "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_score", "obg_tune_set", "obg_tune_get", "obg_probe",
             "obg_batch_create", "obg_batch_run", "obg_batch_info_get", "obg_batch_destroy",
-            "obg_serve_run", "obg_last_error", "obg_version"]
+            "obg_serve_run", "obg_serve_state_bytes", "obg_last_error", "obg_version"]
 
 
 @dataclass
@@ -363,20 +365,34 @@ def obg_batch_create(streams, flags: int = 0, stream=None) -> Batch:
     return Batch(h, keep)
 
 
-def obg_serve_run(streams, arrivals, ingest_fn: int, ingest_ctx: int, speed: float = 1.0,
-                  budget_bytes: int = 32 << 30, max_inflight: int = 3, max_batch_frames: int = 256,
-                  remerge_period: int = 100, remerge_window: int = 50, checksums=None,
-                  watch=None, watch_masks=None, watch_max_frames: int = 0) -> dict:
-    """streams: list of dicts (width, height, depth, n_train, thr=(num, den));
-    arrivals: list of float64 numpy arrays (seconds); checksums: optional uint64
-    numpy array [n_streams, stride]; watch: stream indices whose masks are
-    copied into watch_masks (uint64 numpy arrays [frames, H, ceil(W/64)])."""
-    import numpy as np
+def _serve_streams(streams):
     n = len(streams)
     arr = (ServeStream * n)()
     for i, s in enumerate(streams):
         arr[i] = ServeStream(s["width"], s["height"], s["depth"], s["n_train"], s["thr"][0], s["thr"][1],
                              s.get("region_w", 0), s.get("region_h", 0))
+    return arr
+
+
+def obg_serve_state_bytes(streams, remerge_window: int = 50) -> int:
+    """Bytes of a serving checkpoint of these streams (-1: invalid)."""
+    return load().obg_serve_state_bytes(_serve_streams(streams), len(streams), remerge_window)
+
+
+def obg_serve_run(streams, arrivals, ingest_fn: int, ingest_ctx: int, speed: float = 1.0,
+                  budget_bytes: int = 32 << 30, max_inflight: int = 3, max_batch_frames: int = 256,
+                  remerge_period: int = 100, remerge_window: int = 50, checksums=None,
+                  watch=None, watch_masks=None, watch_max_frames: int = 0,
+                  state_in=None, state_out=None) -> dict:
+    """streams: list of dicts (width, height, depth, n_train, thr=(num, den));
+    arrivals: list of float64 numpy arrays (seconds); checksums: optional uint64
+    numpy array [n_streams, stride]; watch: stream indices whose masks are
+    copied into watch_masks (uint64 numpy arrays [frames, H, ceil(W/64)]);
+    state_in / state_out: optional uint8 numpy arrays of obg_serve_state_bytes
+    bytes (restore a checkpoint before the run / write one after it)."""
+    import numpy as np
+    n = len(streams)
+    arr = _serve_streams(streams)
     arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in arrivals]
     ptrs = (ctypes.POINTER(ctypes.c_double) * n)(*[a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) for a in arrs])
     counts = (ctypes.c_int32 * n)(*[len(a) for a in arrs])
@@ -407,6 +423,13 @@ def obg_serve_run(streams, arrivals, ingest_fn: int, ingest_ctx: int, speed: flo
         cfg.n_watch = len(watch)
         cfg.watch_masks = wm
         cfg.watch_max_frames = watch_max_frames
+    need = None
+    for name, buf in (("state_in", state_in), ("state_out", state_out)):
+        if buf is None:
+            continue
+        need = need if need is not None else obg_serve_state_bytes(streams, remerge_window)
+        assert buf.dtype == np.uint8 and buf.flags.c_contiguous and buf.size >= need > 0, name
+        setattr(cfg, name, buf.ctypes.data)
     st = ServeStats()
     _check(load().obg_serve_run(ctypes.byref(cfg), ctypes.byref(st)))
     return {name: getattr(st, name) for name, _ in ServeStats._fields_}

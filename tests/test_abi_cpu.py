@@ -171,3 +171,24 @@ def test_batch_rejects_bad_streams(lib):
         assert L.obg_batch_create(arr, 1, 0, None, C.byref(out)) == code, (bad, L.obg_last_error())
         assert not out.value
     assert L.obg_batch_create(None, 0, 0, None, C.byref(out)) == -1
+
+
+def test_serve_checkpoint_size_and_refusal(lib):
+    """The checkpoint size follows its stated layout, and a state that is not
+    a checkpoint of the streams is refused before any device work."""
+    import numpy as np
+    streams = [dict(width=64, height=32, depth=3, n_train=5, thr=(1, 2)),
+               dict(width=96, height=64, depth=4, n_train=6, thr=(1, 2), region_w=32, region_h=32)]
+    pad8 = lambda b: (b + 7) // 8 * 8
+    want = 16 + 2 * 48
+    for tree, ring_len in [(64, 10), (512 * 6, 10)]:
+        want += pad8(tree) + pad8(ring_len * tree)
+    assert lib.obg_serve_state_bytes(streams, 10) == want
+    assert lib.obg_serve_state_bytes([dict(streams[0], depth=7)], 10) == -1
+    assert lib.obg_serve_state_bytes(streams, 0) == -1
+    arrivals = [np.array([0.0, 0.1, 0.2]), np.array([0.0, 0.1])]
+    bad = np.zeros(want, dtype=np.uint8)
+    with pytest.raises(lib.ObgError) as e:
+        # the ingest callback is never reached: the state is checked first
+        lib.obg_serve_run(streams, arrivals, 1, 0, remerge_period=10, remerge_window=10, state_in=bad)
+    assert e.value.code == -1

@@ -40,20 +40,25 @@ def _setup():
     return specs, streams, arrivals
 
 
-def _serve(obg, specs, streams, arrivals, which, budget=1 << 30, watch=(), speed=1.0):
+def _serve(obg, specs, streams, arrivals, which, budget=1 << 30, watch=(), speed=1.0, n_frames=None,
+           state_in=None, state_out=None):
+    """n_frames: frames of each stream the source can make and the checksums
+    cover (default: its arrivals; a resumed run's frames continue past them)."""
     from synth.fast import IngestContext
     sp = [specs[i] for i in which]
     st = [streams[i] for i in which]
     ar = [arrivals[i] for i in which]
-    ctx = IngestContext(sp, [len(a) for a in ar], slots=4)
-    stride = max(len(a) for a in ar)
+    nf = [len(a) for a in ar] if n_frames is None else [n_frames[i] for i in which]
+    ctx = IngestContext(sp, nf, slots=4)
+    stride = max(nf)
     sums = np.zeros((len(which), stride), dtype=np.uint64)
     wl = [which.index(w) for w in watch]
     masks = [np.zeros((len(ar[j]), st[j]["height"], (st[j]["width"] + 63) // 64), dtype=np.uint64) for j in wl]
     stats = obg.obg_serve_run(st, ar, ctx.fn, ctx.ctx, speed=speed, budget_bytes=budget, max_inflight=3,
                               max_batch_frames=64, remerge_period=PERIOD, remerge_window=WINDOW,
                               checksums=sums, watch=wl, watch_masks=masks,
-                              watch_max_frames=max((m.shape[0] for m in masks), default=0))
+                              watch_max_frames=max((m.shape[0] for m in masks), default=0),
+                              state_in=state_in, state_out=state_out)
     ctx.close()
     return stats, sums, masks
 
@@ -155,3 +160,45 @@ def test_serve_budget_below_one_frame_is_an_error(env):
     with pytest.raises(obg.ObgError) as e:
         _serve(obg, specs, streams, arrivals, list(range(len(specs))), budget=state + 2048, speed=1000.0)
     assert e.value.code == -4
+
+
+def test_serve_checkpoint_resume(env):
+    """A run cut in two at a checkpoint gives the results of one run: the
+    second run restores every stream's leaf set and ring of trees from the
+    first run's state, and serves the rest of the frames.  Masks (checksums)
+    and the final state are the same bytes as those of one uncut run; the cuts
+    fall inside training, just after it, and between re-merges."""
+    obg, O = env
+    specs, streams, arrivals = _setup()
+    every = list(range(len(specs)))
+    n = [len(a) for a in arrivals]
+    size = obg.obg_serve_state_bytes(streams, WINDOW)
+    assert size > 0
+    full = np.zeros(size, dtype=np.uint8)
+    print(f"[case] serve checkpoint: one run over {sum(n)} frames", flush=True)
+    _, ref, _ = _serve(obg, specs, streams, arrivals, every, speed=1000.0, n_frames=n, state_out=full)
+    cuts = []
+    for i, s in enumerate(streams):
+        T = s["n_train"]
+        options = [T // 2, T, T + 3, T + 2 * PERIOD + 1, n[i] // 2]
+        cuts.append(min(options[i % len(options)], n[i]))
+    first = [a[:c] for a, c in zip(arrivals, cuts)]
+    rest = [a[c:] for a, c in zip(arrivals, cuts)]
+    mid = np.zeros(size, dtype=np.uint8)
+    end = np.zeros(size, dtype=np.uint8)
+    print(f"[case] serve checkpoint: cut at {cuts}", flush=True)
+    _, s1, _ = _serve(obg, specs, streams, first, every, speed=1000.0, n_frames=n, state_out=mid)
+    _, s2, _ = _serve(obg, specs, streams, rest, every, speed=1000.0, n_frames=n, state_in=mid, state_out=end)
+    for i in every:
+        T, c = streams[i]["n_train"], cuts[i]
+        assert np.array_equal(s1[i, T:c], ref[i, T:c]), f"stream {i}: first part"
+        lo = max(c, T)
+        assert np.array_equal(s2[i, lo:n[i]], ref[i, lo:n[i]]), f"stream {i}: resumed part"
+        assert np.count_nonzero(ref[i, T:n[i]]) == n[i] - T
+    assert np.array_equal(end, full), "final state differs from one uncut run"
+    # the state of other streams (same sizes, another width) is refused
+    other = [dict(s, width=s["width"] + 1) if not s["region_w"] else s for s in streams]
+    assert obg.obg_serve_state_bytes(other, WINDOW) == size
+    with pytest.raises(obg.ObgError) as e:
+        _serve(obg, specs, other, rest, every, speed=1000.0, n_frames=n, state_in=mid)
+    assert e.value.code == -1
