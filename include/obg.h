@@ -236,7 +236,9 @@ void obg_batch_destroy(obg_batch *batch);
  * Serving: continuous batching of frames that arrive from many cameras.
  *
  * obg_serve_run drives one run to completion.  Frame f of stream s arrives
- * at arrivals[s][f] simulated seconds (increasing per stream); simulated time
+ * at arrivals[s][f] simulated seconds (finite; a frame that arrives before
+ * its predecessor waits for it, so each stream is served in frame order, and
+ * its latency counts from its own arrival); simulated time
  * runs `speed` times faster than wall time.  The loop admits arrived frames
  * as long as the HBM budget (one arena: every stream's ring and leaf set,
  * plus the buffers of the frames in flight) allows, forms a batch from the

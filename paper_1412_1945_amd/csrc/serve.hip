@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <limits>
 #include <thread>
 #include <vector>
 
@@ -364,11 +365,21 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         }
     }
 
-    // arrivals in time order (frame numbers continue from a restored state)
+    // arrivals in time order (frame numbers continue from a restored state).
+    // A stream's frames are served in frame order: a frame that arrives
+    // before its predecessor is handed to the scheduler with it (its latency
+    // still counts from its own arrival).
     struct Arr { double t; int s, f; };
     std::vector<Arr> arr;
-    for (int s = 0; s < ns; ++s)
-        for (int f = 0; f < cfg->n_arrivals[s]; ++f) arr.push_back({cfg->arrivals[s][f], s, (int)(first[s] + f)});
+    for (int s = 0; s < ns; ++s) {
+        double prev = -std::numeric_limits<double>::infinity();
+        for (int f = 0; f < cfg->n_arrivals[s]; ++f) {
+            const double t = cfg->arrivals[s][f];
+            if (!std::isfinite(t)) return sfail(OBG_EINVAL, "arrival times must be finite");
+            prev = t > prev ? t : prev;
+            arr.push_back({prev, s, (int)(first[s] + f)});
+        }
+    }
     std::stable_sort(arr.begin(), arr.end(), [](const Arr &x, const Arr &y) { return x.t < y.t; });
 
     uint8_t *arena_mem = nullptr;

@@ -192,3 +192,7 @@ def test_serve_checkpoint_size_and_refusal(lib):
         # the ingest callback is never reached: the state is checked first
         lib.obg_serve_run(streams, arrivals, 1, 0, remerge_period=10, remerge_window=10, state_in=bad)
     assert e.value.code == -1
+    with pytest.raises(lib.ObgError) as e:
+        lib.obg_serve_run(streams, [np.array([0.0, float("nan"), 0.2]), arrivals[1]], 1, 0,
+                          remerge_period=10, remerge_window=10)
+    assert e.value.code == -1 and "finite" in str(e.value)
