@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -120,14 +122,17 @@ def host_cpu():
     return max(n, 1), model
 
 
-def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, budget_s):
+def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, budget_s,
+                 gpu_leaf=None, gpu_mask=None):
     """The oracle as it is, single-threaded: trees of every training frame, the
     merge, then test frames (fetched one at a time) until `budget_s` seconds
     have passed or `n_test` frames are classified.  Two more legs use all the
     host's threads (the oracle's C calls release the GIL): up to 8 test frames
     per thread classified with the same model, and the training frames' trees
     built with the frames dealt to the threads.  They are reported beside the
-    single-threaded figure."""
+    single-threaded figure.  With gpu_leaf (the GPU's merged leaf set) and
+    gpu_mask(i) (the GPU's mask of test frame i), the oracle's leaf set and
+    every mask it computed are compared with them, outside the timed calls."""
     from oracle import octree
     t0 = time.perf_counter()
     f = octree.Forest(spec.width, spec.height, depth, region[0], region[1])
@@ -136,11 +141,14 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
     t_train = time.perf_counter() - t0
     done = 0
     t_cls = 0.0
+    masks_equal = True
     while done < n_test and t_train + t_cls < budget_s:
         fr = test_frame(done)
         t1 = time.perf_counter()
-        model.classify(fr)
+        m = model.classify(fr)
         t_cls += time.perf_counter() - t1
+        if gpu_mask is not None:
+            masks_equal = masks_equal and bool(np.array_equal(m, gpu_mask(done).reshape(m.shape)))
         done += 1
     dt = t_train + t_cls
     px = (len(host_train) + done) * spec.pixels
@@ -152,6 +160,10 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
            "train_gpixel_s": round(len(host_train) * spec.pixels / t_train / 1e9, 5),
            "classify_gpixel_s": round(done * spec.pixels / t_cls / 1e9, 5) if done else None,
            "cpu_model": cpu_model, "host_threads": threads}
+    if gpu_leaf is not None:
+        want = model.leafset()
+        out["verified"] = {"leaf_set_equal": bool(np.array_equal(want, gpu_leaf.reshape(want.shape))),
+                           "test_frames": done, "masks_equal": masks_equal}
     if threads > 1 and done:
         from concurrent.futures import ThreadPoolExecutor
         frames = [test_frame(i) for i in range(min(done, 8 * threads))]
@@ -679,7 +691,9 @@ def main():
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         host_train = list(train.cpu().numpy())
         out["cpu_baseline"] = cpu_baseline(host_train, lambda i: test[i].cpu().numpy(), N, spec, depth,
-                                           num, den, (rw, rh), a.cpu_seconds)
+                                           num, den, (rw, rh), a.cpu_seconds,
+                                           gpu_leaf=leaf.cpu().numpy().view(np.uint32),
+                                           gpu_mask=lambda i: mask[i].cpu().numpy().view(np.uint64))
     print(json.dumps(out), flush=True)
 
 
