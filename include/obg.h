@@ -314,7 +314,9 @@ typedef struct obg_serve_config {
     int32_t watch_max_frames;
     /* Checkpoint, NULLABLE (host buffers of obg_serve_state_bytes bytes).
        state_out receives, when the run ends, every stream's merged leaf set,
-       its ring of per-frame trees and the index of its next frame.  state_in
+       its ring of per-frame trees and the index of its next frame (region
+       streams may hold their bitsets in the kernels' own bit order: a state
+       is for restoring, not for reading).  state_in
        restores such a state (written for the same streams: geometry, depth,
        n_train, regions, and the same remerge_window) before the first frame
        is admitted; arrivals[s][i] is then frame next_frame[s] + i, and every

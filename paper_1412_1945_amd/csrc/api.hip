@@ -178,9 +178,10 @@ int region_chunk_cols(const Geo &g, int mode, int lay, int64_t rows_sf, int64_t 
 
 // lists: frames, masks and trees through per-frame pointer arrays (the
 // geometry must pass strip_ok; every (frame, strip) is one work item and its
-// trees are stored whole)
+// trees are stored whole); native: with lists, bitsets in the compact order
 int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, const uint32_t *leaf,
-               uint64_t *mask, uint32_t *occ, uint32_t *counts, hipStream_t st, const FrameLists *lists = nullptr) {
+               uint64_t *mask, uint32_t *occ, uint32_t *counts, hipStream_t st, const FrameLists *lists = nullptr,
+               bool native = false) {
     hipError_t e;
     const int64_t occ_words = (int64_t)n_frames * g.n_regions * g.words;
     if (mode & MODE_COUNTS) {
@@ -345,6 +346,8 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         a.rgb_list = lists->rgb;
         a.mask_list = lists->mask;
         a.occ_list = lists->occ;
+        if (native && lay != LAY_COMPACT) return fail(OBG_EINVAL, "internal: native order needs compact tables");
+        a.native = native ? 1 : 0;
     }
     if ((mode & MODE_OCC) && !store) {
         if ((e = launch_fill_u32(occ, occ_words, 0u, st)) != hipSuccess) return hip_fail(e, "zero occupancy");
@@ -368,8 +371,16 @@ bool obg::pixels_list_ok(const obg_geom *g, int mode) {
     return mode == MODE_OCC || mode == (MODE_MASK | MODE_OCC) ? strip_ok(o, mode, &lay) : false;
 }
 
+bool obg::pixels_list_native_ok(const obg_geom *g) {
+    Geo o{};
+    int lay_occ = 0, lay_both = 0;
+    if (check_geom(g, &o, true) != OBG_OK || o.reg_cols < 2) return false;
+    if (!strip_ok(o, MODE_OCC, &lay_occ) || !strip_ok(o, MODE_MASK | MODE_OCC, &lay_both)) return false;
+    return lay_occ == LAY_COMPACT && lay_both == LAY_COMPACT;
+}
+
 int obg::run_pixels_list(const obg_geom *g, int mode, const FrameLists &l, int32_t n_frames, const uint32_t *leaf,
-                    hipStream_t stream) {
+                    hipStream_t stream, bool native) {
     Geo o{};
     int rc = check_geom(g, &o, true);
     if (rc != OBG_OK) return rc;
@@ -377,7 +388,7 @@ int obg::run_pixels_list(const obg_geom *g, int mode, const FrameLists &l, int32
     if (o.reg_cols < 2) return fail(OBG_EINVAL, "internal: frame lists need several regions per row");
     if (n_frames < 1 || !l.rgb || !l.occ || ((mode & MODE_MASK) && (!l.mask || !leaf)))
         return fail(OBG_EINVAL, "internal: frame lists");
-    return run_pixels(o, mode, nullptr, n_frames, leaf, nullptr, nullptr, nullptr, stream, &l);
+    return run_pixels(o, mode, nullptr, n_frames, leaf, nullptr, nullptr, nullptr, stream, &l, native);
 }
 
 extern "C" {

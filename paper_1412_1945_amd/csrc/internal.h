@@ -46,6 +46,9 @@ struct StripArgs {
     const uint8_t *const *rgb_list;
     uint64_t *const *mask_list;
     uint32_t *const *occ_list;
+    // with frame lists and compact tables: leaf set and trees in HBM are in
+    // the compact LDS order instead of key order (copied as they are)
+    int32_t native;
 };
 
 // Per-pixel fallback for any depth 1..8 and any region size.
@@ -117,7 +120,10 @@ struct FrameLists {
     uint32_t *const *occ;
 };
 bool pixels_list_ok(const obg_geom *g, int mode);
+// Both modes take frame lists with compact tables: the geometry's bitsets
+// can stay in the compact LDS order (native) from pass to pass.
+bool pixels_list_native_ok(const obg_geom *g);
 int run_pixels_list(const obg_geom *g, int mode, const FrameLists &l, int32_t n_frames, const uint32_t *leaf,
-                    hipStream_t stream);
+                    hipStream_t stream, bool native = false);
 
 }  // namespace obg

@@ -57,6 +57,8 @@ strip_kernel(StripArgs a) {
     uint32_t *leaf_lds = REGION ? dyn_lds : st_leaf;
     uint32_t *occ_lds = REGION ? dyn_lds + (MASK ? max_tiles * LW : 0) : st_occ;
     const bool store = a.occ_store != 0;
+    // bitsets kept in the compact LDS order (frame lists of the serving runtime)
+    const bool native = LIST && PAD == LAY_COMPACT && a.native != 0;
 
     // work items: a contiguous range per workgroup, or interleaved so that
     // the items in flight at any moment are neighbours in memory
@@ -97,11 +99,12 @@ strip_kernel(StripArgs a) {
         const bool new_seg = (s != cur_s) || (f != cur_f);
         if (OCC && new_seg && cur_f >= 0) {
             __syncthreads();
-            occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store);
+            occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store,
+                                 native);
         }
         if (MASK && s != cur_s) {
             __syncthreads();
-            leaf_to_lds<D, PAD>(a.leaf + reg0 * KW, leaf_lds, tiles, tid, BLOCK);
+            leaf_to_lds<D, PAD>(a.leaf + reg0 * KW, leaf_lds, tiles, tid, BLOCK, native);
         }
         if (OCC && new_seg) {
             __syncthreads();
@@ -131,7 +134,8 @@ strip_kernel(StripArgs a) {
     }
     if (OCC && cur_f >= 0) {
         __syncthreads();
-        occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store);
+        occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store,
+                             native);
     }
 }
 

@@ -176,7 +176,8 @@ struct StreamDev {
     StripArgs a{};
     int words = 0, valid_bits = 32, groups = 0;
     int n_regions = 1;
-    bool region = false;      // one tree per region: the one-stream passes serve it
+    bool region = false;      // one tree per region: the region passes serve it
+    bool native = false;      // region rings and leaf set kept in the compact LDS order
     obg_geom geom{};          // for those passes
 };
 
@@ -322,6 +323,11 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         sd.geom.depth = c.depth;
         sd.geom.region_w = c.region_w;
         sd.geom.region_h = c.region_h;
+        // the rings and leaf set of a region stream never leave the library:
+        // where every pass of the stream runs over frame lists with compact
+        // tables they stay in that order, and the flushes and table loads
+        // copy words (merges count bit by bit, whatever the order)
+        sd.native = sd.region && pixels_list_native_ok(&sd.geom);
         StripArgs &a = sd.a;
         a.width = c.width;
         a.height = c.height;
@@ -611,7 +617,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                         FrameLists fl{reinterpret_cast<const uint8_t *const *>(sl.d_lists + i0),
                                       reinterpret_cast<uint64_t *const *>(sl.d_lists + maxf + i0),
                                       reinterpret_cast<uint32_t *const *>(sl.d_lists + 2 * maxf + i0)};
-                        ok = run_pixels_list(&sd.geom, mode, fl, q - p, leaf, st) == OBG_OK;
+                        ok = run_pixels_list(&sd.geom, mode, fl, q - p, leaf, st, sd.native) == OBG_OK;
                     } else {
                         for (int r = p; ok && r < q; ++r) {
                             const SchedFrame &fr = F[sl.order[r]];

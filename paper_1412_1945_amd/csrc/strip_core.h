@@ -11,13 +11,22 @@ namespace obg {
 
 // The bits of one key-order word kw are keys 32*kw + b; their LDS indices are
 // lds_from_key(32*kw) | lds_from_key(b) because the map permutes index bits.
+// native: the bitsets in HBM are already in the compact LDS order (the
+// serving runtime's own rings and leaf sets); words are copied as they are.
 template <int D, int PAD>
 __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, uint32_t *lds,
-                                            int n_tiles, int tid, int nt) {
+                                            int n_tiles, int tid, int nt, bool native = false) {
     constexpr int KW = leaf_words(D);
     constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
+    if (PAD == LAY_COMPACT && native) {
+        static_assert(PAD != LAY_COMPACT || LW == KW, "compact tables are key-sized");
+        const uint32_t valid = LC < 32 ? (1u << (LC & 31)) - 1u : 0xFFFFFFFFu;
+        for (int i = tid; i < n_tiles * KW; i += nt) lds[i] = leaf[i] & valid;
+        __syncthreads();
+        return;
+    }
     for (int i = tid; i < n_tiles * LW; i += nt) lds[i] = 0;
     __syncthreads();
     for (int i = tid; i < n_tiles * KW; i += nt) {
@@ -44,11 +53,22 @@ __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, u
 // other workgroups also write.
 template <int D, int PAD>
 __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__restrict__ occ,
-                                             int n_tiles, int tid, int nt, bool store = false) {
+                                             int n_tiles, int tid, int nt, bool store = false,
+                                             bool native = false) {
     constexpr int KW = leaf_words(D);
     constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
+    if (PAD == LAY_COMPACT && native) {
+        for (int i = tid; i < n_tiles * KW; i += nt) {
+            const uint32_t w = lds[i];
+            if (store)
+                occ[i] = w;
+            else if (w)
+                atomicOr(&occ[i], w);
+        }
+        return;
+    }
     for (int i = tid; i < n_tiles * KW; i += nt) {
         const int c = i / KW;
         const int kw = i - c * KW;
