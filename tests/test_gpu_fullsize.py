@@ -86,3 +86,43 @@ def test_region_4k_full(env):
     """3840x2160 in 32x32 regions, depth 4, 30 training + 500 test frames."""
     from synth.frames import cfg2
     _run_and_check(env, cfg2(), whole_frames=[0, 499], n_samples=20000, seed=2)
+
+
+def test_largest_frame(env):
+    """One frame close to the format's limit (frame_pitch below 2 GiB):
+    24576 x 24000, depth 5, two training frames and one test frame.  Training
+    frames use only colours whose channels have bit 5 clear, the test frame
+    any colour, so its mask holds both classes.  Trees, leaf set and the
+    whole mask equal the oracle's."""
+    obg, O = env
+    W, H, d = 24576, 24000, 5
+    g = obg.FrameGeom(W, H, d)
+    assert g.frame_pitch < (1 << 31)
+    print(f"[case] largest frame {W}x{H} ({g.frame_pitch / 2**30:.2f} GiB)", flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(24576)
+    frames = torch.randint(0, 256, (3, H, g.row_pitch), dtype=torch.uint8, device="cuda", generator=gen)
+    frames[:2] &= 0xDF
+    occ = obg.empty_occ(g, 2)
+    leaf = obg.empty_leafset(g)
+    mask = obg.empty_mask(g, 1)
+    obg.obg_train_frame(g, frames[:2], 2, occ)
+    obg.obg_merge(g, occ, 2, 0, 2, 1, 2, leaf)
+    obg.obg_classify(g, frames[2:], 1, leaf, mask)
+    torch.cuda.synchronize()
+    host = frames.cpu().numpy()
+    del frames
+    torch.cuda.empty_cache()
+    print("[case] largest frame: oracle", flush=True)
+    forest = O.Forest(W, H, d)
+    idx = forest.add_frames([host[0], host[1]])
+    g_occ = occ.cpu().numpy().view(np.uint32)
+    for i in idx:
+        assert np.array_equal(g_occ[i], forest.export(i)), f"occupancy of training frame {i}"
+    model = forest.merge(idx, 1, 2)
+    assert np.array_equal(leaf.cpu().numpy().view(np.uint32), model.leafset()), "merged leaf set"
+    want = model.classify(host[2])
+    got = mask.cpu().numpy().view(np.uint64)[0]
+    assert np.array_equal(got, want), "mask of the test frame"
+    ones = int(np.unpackbits(want.view(np.uint8)).sum())
+    assert 0 < ones < W * H
