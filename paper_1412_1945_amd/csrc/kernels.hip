@@ -35,7 +35,7 @@ __device__ __forceinline__ uint32_t *frame_occ(const StripArgs &a, int f, int kw
 // separate instance, so the other kernels keep their registers)
 template <int D, int MODE, int BLOCK, int PAD, bool REGION, bool LIST = false>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
-    (MODE == MODE_MASK && D == 5) ? 8 : ((MODE == (MODE_MASK | MODE_OCC) && BLOCK == 512) ? 4 : 1)))) void
+    (MODE == MODE_MASK && D == 5) ? (BLOCK == 512 ? 8 : 4) : ((MODE == (MODE_MASK | MODE_OCC) && BLOCK == 512) ? 4 : 1)))) void
 strip_kernel(StripArgs a) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
