@@ -51,10 +51,19 @@ struct BatchArgs {
     int32_t stage_mask;
 };
 
-// Item `it` belongs to the last stream whose first item is <= it.
+// Item `it` belongs to the last stream whose first item is <= it.  A
+// workgroup's next item is nearly always in the stream of its last one
+// (`hint`), which is checked first: the search is a chain of dependent loads
+// that would cost about as much as streaming a small item.
 template <int MODE>
-__device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it) {
+__device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it, int hint = -1) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    if (hint >= 0) {
+        const BatchStreamDev &h = b.streams[hint];
+        const int64_t first = MASK ? h.citem0 : h.titem0;
+        const int64_t n = MASK ? (int64_t)h.cspans * h.n_test : (int64_t)h.tspans * h.n_train;
+        if (it >= first && it < first + n) return hint;
+    }
     int lo = 0, hi = b.n_streams - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -135,7 +144,7 @@ __global__ __launch_bounds__(BLOCK) void batch_depth_kernel(BatchArgs b) {
     }
     int cur = -1;
     for (int64_t it = i0; it < i1; it += istep) {
-        const int s = stream_of<MODE>(b, it);
+        const int s = stream_of<MODE>(b, it, cur);
         const BatchStreamDev &sd = b.streams[s];
         const int64_t local = it - (MASK ? sd.citem0 : sd.titem0);
         item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, s != cur);
@@ -160,7 +169,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs b) {
     }
     int cur = -1;
     for (int64_t it = i0; it < i1; it += istep) {
-        const int s = stream_of<MODE>(b, it);
+        const int s = stream_of<MODE>(b, it, cur);
         const BatchStreamDev &sd = b.streams[s];
         const int64_t local = it - (MASK ? sd.citem0 : sd.titem0);
         const bool fresh = s != cur;
