@@ -348,9 +348,9 @@ int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
 int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams, int32_t remerge_window);
 
 /*
- * Launch-shape knobs of the pixel kernels, process-wide, for the autotuner
- * (0 restores the built-in default).  They change speed only: every setting
- * gives the same bytes.
+ * Launch-shape knobs of the pixel kernels and batches, process-wide, for the
+ * autotuner (0 restores the built-in default).  They change speed only:
+ * every setting gives the same bytes.
  *   OBG_TUNE_TRAIN_BLOCK        threads per workgroup of occupancy-only
  *                               passes: 256 or 1024 (default 1024; 256 for
  *                               region work items of fewer than 2048
@@ -387,6 +387,10 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
  *                               item per (frame, chunk) whose words are
  *                               stored (default); 2 = chunks only where a
  *                               row's tables do not fit in LDS
+ *   OBG_TUNE_BATCH_PER_DEPTH    shape a batch starts from (obg_batch_create,
+ *                               before any autotuning): 1 = one persistent
+ *                               launch per phase (default), 2 = one launch
+ *                               per depth present and phase
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1
@@ -398,7 +402,8 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
 #define OBG_TUNE_INTERLEAVE          7
 #define OBG_TUNE_MASK_STAGE          8
 #define OBG_TUNE_REGION_CHUNKS       9
-#define OBG_TUNE_COUNT               10
+#define OBG_TUNE_BATCH_PER_DEPTH     10
+#define OBG_TUNE_COUNT               11
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 

@@ -203,17 +203,28 @@ __global__ __launch_bounds__(256) void batch_zero_kernel(const BatchStreamDev *s
 }
 
 // Order-independent checksum of every output word (autotuner cross-check).
+// Each word is mixed with its stream, its kind and its position before a
+// non-linear finaliser, so a word written to the wrong place (or the wrong
+// stream) changes the sum.
+__device__ __forceinline__ unsigned long long check_mix(uint64_t word, uint64_t where) {
+    uint64_t x = word ^ (where * 0x9E3779B97F4A7C15ull);
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
 __global__ __launch_bounds__(256) void batch_checksum_kernel(const BatchStreamDev *streams, unsigned long long *out) {
     const BatchStreamDev &sd = streams[blockIdx.y];
     const int64_t nm = (int64_t)sd.n_test * sd.a.height * sd.a.mask_row_words;
     const int64_t no = (int64_t)sd.n_train * sd.words;
+    const uint64_t base = (uint64_t)blockIdx.y << 42;   // stream; kind in bits 40..41
     unsigned long long h = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nm; i += (int64_t)gridDim.x * blockDim.x)
-        h += (sd.mask[i] ^ (0x9E3779B97F4A7C15ull * (uint64_t)(i + 1))) * 0xBF58476D1CE4E5B9ull;
+        h += check_mix(sd.mask[i], base + (uint64_t)i);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < no; i += (int64_t)gridDim.x * blockDim.x)
-        h += ((uint64_t)sd.occ[i] + 0x632BE59BD9B4E019ull * (uint64_t)(i + 7)) * 0x94D049BB133111EBull;
+        h += check_mix(sd.occ[i], base + (1ull << 40) + (uint64_t)i);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.words; i += (int64_t)gridDim.x * blockDim.x)
-        h += ((uint64_t)sd.leaf[i] + 0x2545F4914F6CDD1Dull * (uint64_t)(i + 3)) * 0xD6E8FEB86659FD93ull;
+        h += check_mix(sd.leaf[i], base + (2ull << 40) + (uint64_t)i);
     atomicAdd(out, h);
 }
 
@@ -622,7 +633,7 @@ int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t
     hipError_t e = hipMalloc(&b->d, sizeof(BatchStreamDev) * n_streams);
     if (e == hipSuccess) e = hipMalloc(&b->d_sum, sizeof(unsigned long long));
     if (e != hipSuccess) { destroy(b); return bfail(OBG_ENOMEM, "descriptor allocation: %s", hipGetErrorString(e)); }
-    b->shape = Shape{256, 4, 4, 512, 2, 832, 1, 0};
+    b->shape = Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 1) == 2 ? 1 : 0};
     int rc = plan_items(b);
     if (rc == OBG_OK && (flags & OBG_BATCH_AUTOTUNE)) rc = autotune(b, stream);
     if (rc == OBG_OK && !(flags & OBG_BATCH_NO_GRAPH)) {

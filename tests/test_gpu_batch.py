@@ -58,14 +58,21 @@ def _one_stream_reference(obg, s):
     return occ, leaf, mask
 
 
-@pytest.mark.parametrize("flags", [0, 2, 1], ids=["graph", "no_graph", "autotune"])
-def test_batch_equals_one_stream_calls_and_oracle(env, flags):
+@pytest.mark.parametrize("flags,per_depth", [(0, 1), (2, 1), (1, 1), (0, 2), (2, 2)],
+                         ids=["graph", "no_graph", "autotune", "per_depth_graph", "per_depth_no_graph"])
+def test_batch_equals_one_stream_calls_and_oracle(env, flags, per_depth):
     obg, O = env
-    streams = _mixed(obg, 11 + flags)
-    print(f"[case] batch flags={flags} streams={len(streams)}", flush=True)
-    batch = obg.obg_batch_create(streams, flags=flags)
+    streams = _mixed(obg, 11 + flags + 10 * (per_depth - 1))
+    print(f"[case] batch flags={flags} per_depth={per_depth} streams={len(streams)}", flush=True)
+    obg.obg_tune_set("batch_per_depth", per_depth)
+    try:
+        batch = obg.obg_batch_create(streams, flags=flags)
+    finally:
+        obg.obg_tune_set("batch_per_depth", 0)
     info = batch.info()
     assert info["graph"] == (0 if flags & 2 else 1)
+    if not flags & 1:
+        assert info["per_depth_launches"] == per_depth - 1
     for rep in range(2):                   # outputs are rewritten completely on every run
         for s in streams:
             s["occ"].fill_(-1)
