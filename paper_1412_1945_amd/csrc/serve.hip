@@ -157,8 +157,14 @@ __global__ __launch_bounds__(256) void serve_checksum_kernel(const ServeFrameDev
     const ServeFrameDev &fd = frames[blockIdx.y];
     const int64_t n = (int64_t)fd.a.height * fd.a.mask_row_words;
     unsigned long long h = 0;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        h += (fd.mask[i] ^ (0x9E3779B97F4A7C15ull * (uint64_t)(i + 1))) * 0xBF58476D1CE4E5B9ull;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        // each word mixed with its position through a non-linear finaliser,
+        // so words moved or bits exchanged between words change the sum
+        uint64_t x = fd.mask[i] ^ ((uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        h += x ^ (x >> 31);
+    }
     atomicAdd(&out[blockIdx.y], h);
 }
 
