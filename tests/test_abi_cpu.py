@@ -196,3 +196,26 @@ def test_serve_checkpoint_size_and_refusal(lib):
         lib.obg_serve_run(streams, [np.array([0.0, float("nan"), 0.2]), arrivals[1]], 1, 0,
                           remerge_period=10, remerge_window=10)
     assert e.value.code == -1 and "finite" in str(e.value)
+
+
+def test_tune_keys_match_header_and_refuse_bad_values(lib):
+    """Every launch knob the header defines has the same number in the
+    binding; values round-trip; unknown keys and negative values are refused."""
+    src = open(HEADER).read()
+    defs = {m.group(1).lower(): int(m.group(2))
+            for m in re.finditer(r"#define OBG_TUNE_([A-Z_]+)\s+(\d+)", src)}
+    count = defs.pop("count")
+    assert lib.TUNE_KEYS == defs
+    assert sorted(defs.values()) == list(range(count))
+    L = lib.load()
+    for key, k in defs.items():
+        assert L.obg_tune_get(k) == 0, key
+        assert L.obg_tune_set(k, 2) == 0, key
+        assert lib.obg_tune_get(key) == 2, key
+        lib.obg_tune_set(key, 0)
+        assert L.obg_tune_get(k) == 0, key
+    assert L.obg_tune_set(count, 1) != 0
+    assert L.obg_tune_set(-1, 1) != 0
+    assert L.obg_tune_get(count) == -1
+    assert L.obg_tune_set(0, -1) != 0
+    assert L.obg_tune_get(0) == 0
