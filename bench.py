@@ -50,6 +50,8 @@ def parse():
                         "shared with the frame source)")
     p.add_argument("--serve-batch", type=int, default=256, help="most frames per batch (served)")
     p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-extra-legs", action="store_true",
+                   help="plain workloads: skip the batched and served legs that the default run appends")
     p.add_argument("--cpu-seconds", type=float, default=15.0,
                    help="time budget of the oracle's timed sample (all training frames, then test frames)")
     p.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "classify_traffic.json"),
@@ -123,7 +125,7 @@ def host_cpu():
 
 
 def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, budget_s,
-                 gpu_leaf=None, gpu_mask=None):
+                 gpu_leaf=None, gpu_mask=None, gpu_classify=None):
     """The oracle as it is, single-threaded: trees of every training frame, the
     merge, then test frames (fetched one at a time) until `budget_s` seconds
     have passed or `n_test` frames are classified.  Two more legs use all the
@@ -132,7 +134,11 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
     built with the frames dealt to the threads.  They are reported beside the
     single-threaded figure.  With gpu_leaf (the GPU's merged leaf set) and
     gpu_mask(i) (the GPU's mask of test frame i), the oracle's leaf set and
-    every mask it computed are compared with them, outside the timed calls."""
+    every mask it computed are compared with them, outside the timed calls.
+    With gpu_classify(leaf) (the same classify launch over all test frames
+    against another leaf set; returns the GPU's mask of test frame i), the
+    oracle's merged tree of another seed's small stream is the model, whose
+    masks hold both classes, and 16 test frames are compared whole."""
     from oracle import octree
     t0 = time.perf_counter()
     f = octree.Forest(spec.width, spec.height, depth, region[0], region[1])
@@ -142,6 +148,7 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
     done = 0
     t_cls = 0.0
     masks_equal = True
+    fg_own = 0
     while done < n_test and t_train + t_cls < budget_s:
         fr = test_frame(done)
         t1 = time.perf_counter()
@@ -149,6 +156,7 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
         t_cls += time.perf_counter() - t1
         if gpu_mask is not None:
             masks_equal = masks_equal and bool(np.array_equal(m, gpu_mask(done).reshape(m.shape)))
+            fg_own += int(np.unpackbits(m.view(np.uint8)).sum())
         done += 1
     dt = t_train + t_cls
     px = (len(host_train) + done) * spec.pixels
@@ -163,7 +171,23 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
     if gpu_leaf is not None:
         want = model.leafset()
         out["verified"] = {"leaf_set_equal": bool(np.array_equal(want, gpu_leaf.reshape(want.shape))),
-                           "test_frames": done, "masks_equal": masks_equal}
+                           "test_frames": done, "masks_equal": masks_equal, "foreground_bits_compared": fg_own}
+    if gpu_classify is not None:
+        from oracle import models
+        other = models.foreign_model(spec.width, spec.height, depth, region[0], region[1])
+        g_mask = gpu_classify(models.foreign_leafset(depth, other.n_regions))
+        k = min(16, n_test)
+        eq, fg = True, 0
+        for j in range(k):
+            i = j * n_test // k
+            want = other.classify(test_frame(i))
+            eq = eq and bool(np.array_equal(want, g_mask(i).reshape(want.shape)))
+            fg += int(np.unpackbits(want.view(np.uint8)).sum())
+        out.setdefault("verified", {})["discriminating"] = {
+            "model": f"merged tree of a {models.MODEL_SIDE[depth]}x{models.MODEL_SIDE[depth]} stream of another "
+                     f"seed (oracle), same classify launch over all {n_test} test frames",
+            "test_frames": k, "masks_equal": eq, "foreground_bits_compared": fg,
+            "foreground_fraction": round(fg / (k * spec.pixels), 4)}
     if threads > 1 and done:
         from concurrent.futures import ThreadPoolExecutor
         frames = [test_frame(i) for i in range(min(done, 8 * threads))]
@@ -195,20 +219,20 @@ def cpu_baseline(host_train, test_frame, n_test, spec, depth, num, den, region, 
     return out
 
 
-def run_batched(a):
+def batched_leg(a, steps, warmup, verify_oracle=False):
     """64 streams of mixed resolution, depth, T and threshold: the batched form
-    (one persistent launch per step, graph-captured, autotuned) against the
-    plain form (one launch per stream and frame) and one launch per stream."""
+    (one plan: a persistent launch per step, graph-captured, autotuned on the
+    work) against the plain form (one launch per stream and frame) and one
+    launch per stream.  Returns the figures as a dict."""
     import ctypes
     import torch
     from paper_1412_1945_amd import obg
     from synth import frames as S
     from synth.fast import make_frames_gpu
-    obg.load()
     L = obg.load()
     wl = S.cfg3(n_streams=a.streams)
     streams = []
-    print(f"# generating {len(wl.streams)} streams on the GPU", file=sys.stderr, flush=True)
+    print(f"# batched: generating {len(wl.streams)} streams on the GPU", file=sys.stderr, flush=True)
     for spec, d, thr in zip(wl.streams, wl.depth, wl.thr):
         g = obg.FrameGeom(spec.width, spec.height, d)
         fr = torch.empty((spec.n_frames, spec.height, spec.row_pitch), dtype=torch.uint8, device="cuda")
@@ -226,19 +250,23 @@ def run_batched(a):
     stream = torch.cuda.current_stream()
     hs = ctypes.c_void_p(stream.cuda_stream)
 
-    print("# batch create (autotune)", file=sys.stderr, flush=True)
-    batch = obg.obg_batch_create(streams, flags=obg.BATCH_AUTOTUNE)
-    info = batch.info()
-    for _ in range(a.warmup):
-        batch.run()
+    print("# batched: plan create and tune", file=sys.stderr, flush=True)
+    plan = obg.obg_plan_create([{"geom": s["geom"], "thr": s["thr"], "max_train": s["n_train"],
+                                 "max_test": s["n_test"]} for s in streams])
+    items = obg.work_items([dict(s, stream=i) for i, s in enumerate(streams)])
+    plan.tune(items)
+    info = plan.info()
+    for _ in range(warmup):
+        plan.run(items)
     torch.cuda.synchronize()
     e0, e1 = ev(), ev()
     e0.record(stream)
-    for _ in range(a.steps):
-        batch.run()
+    for _ in range(steps):
+        plan.run(items)
     e1.record(stream)
     torch.cuda.synchronize()
-    ms_batched = e0.elapsed_time(e1) / a.steps
+    ms_batched = e0.elapsed_time(e1) / steps
+    status_ok = obg.item_status(items) == [obg.ITEM_OK] * len(streams)
 
     # plain: one call per stream and frame, raw C calls with prepared arguments
     calls = []
@@ -279,52 +307,86 @@ def run_batched(a):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps, (time.perf_counter() - t0) * 1e3 / reps
 
-    print("# plain per frame", file=sys.stderr, flush=True)
+    print("# batched: plain per frame", file=sys.stderr, flush=True)
     ms_plain, host_plain = timed(plain_per_frame, 2)
     same = all(torch.equal(s["occ"], s["p_occ"]) and torch.equal(s["leafset"], s["p_leaf"])
                and torch.equal(s["mask"], s["p_mask"]) for s in streams)
-    # the same per-frame launches replayed from a captured graph: no host
-    # overhead left, only the GPU time of one kernel per frame
-    print("# plain per frame, graph-replayed", file=sys.stderr, flush=True)
-    gph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(gph):
-        plain_per_frame(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
-    torch.cuda.synchronize()
-    ms_plain_graph, _ = timed(gph.replay, 3)
-    same3 = all(torch.equal(s["mask"], s["p_mask"]) and torch.equal(s["leafset"], s["p_leaf"]) for s in streams)
-    del gph
-    print("# plain per stream", file=sys.stderr, flush=True)
+    print("# batched: plain per stream", file=sys.stderr, flush=True)
     ms_stream, _ = timed(plain_per_stream, 3)
-    same2 = all(torch.equal(s["mask"], s["p_mask"]) for s in streams)
-    bytes_step = 3 * px + px_test // 8
+    same2 = all(torch.equal(s["mask"], s["p_mask"]) and torch.equal(s["leafset"], s["p_leaf"]) for s in streams)
+    bytes_step = 3 * px + px_test // 8 + sum(s["n_train"] * s["geom"].words * 4 for s in streams)
     out = {
-        "metric": "train+classify Gpixel/s (batched)",
-        "value": round(px / (ms_batched * 1e-3) / 1e9, 3),
-        "unit": "Gpixel/s",
-        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": round(ms_batched, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u8", "data": "synthetic",
-        "config": {"workload": wl.name, "streams": len(streams), "train_gpx": round(px_train / 1e9, 3),
-                   "test_gpx": round(px_test / 1e9, 3)},
-        "batched": {"ms": round(ms_batched, 3), "gpixel_s": round(px / (ms_batched * 1e-3) / 1e9, 1),
-                    "info": info},
+        "workload": wl.name, "streams": len(streams),
+        "train_gpx": round(px_train / 1e9, 3), "test_gpx": round(px_test / 1e9, 3),
+        "ms": round(ms_batched, 3), "gpixel_s": round(px / (ms_batched * 1e-3) / 1e9, 1),
+        "plan": info,
         "plain_per_frame": {"ms": round(ms_plain, 3), "host_ms": round(host_plain, 3),
                             "gpixel_s": round(px / (ms_plain * 1e-3) / 1e9, 1),
                             "launches": sum(c[9] + c[10] + 1 for c in calls)},
-        "plain_per_frame_graph": {"ms": round(ms_plain_graph, 3),
-                                  "gpixel_s": round(px / (ms_plain_graph * 1e-3) / 1e9, 1)},
         "plain_per_stream": {"ms": round(ms_stream, 3), "gpixel_s": round(px / (ms_stream * 1e-3) / 1e9, 1)},
         "batched_vs_plain": round(ms_plain / ms_batched, 2),
-        "batched_vs_plain_graph": round(ms_plain_graph / ms_batched, 2),
         "batched_vs_per_stream": round(ms_stream / ms_batched, 2),
-        "bit_exact_vs_plain": bool(same and same2 and same3),
+        "bit_exact_vs_plain": bool(same and same2 and status_ok),
         "roofline": {"bound": "hbm", "achieved": round(bytes_step / (ms_batched * 1e-3) / 1e9, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(bytes_step / (ms_batched * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "whole batch (train + merge + classify)"},
+                     "traffic": None, "kernel": "whole batched run (prepare + train + merge + classify)",
+                     "bytes": bytes_step},
     }
-    batch.close()
+    if verify_oracle:
+        out["cpu_baseline"] = batched_cpu_baseline(streams)
+    plan.close()
+    del streams, calls
+    torch.cuda.empty_cache()
+    return out
+
+
+def batched_cpu_baseline(streams, budget_s=10.0):
+    """The oracle on the batched workload, single-threaded, smallest streams
+    first until the time budget is spent: each stream's trees and merge, then
+    two of its test frames.  Its leaf sets and masks are compared with the
+    batched run's outputs (outside the timed calls)."""
+    import numpy as np
+    from oracle import octree
+    t_all = t_run = 0.0
+    px = 0
+    order = sorted(range(len(streams)), key=lambda i: (streams[i]["geom"].width * streams[i]["geom"].height, i))
+    checked, ok, fg = 0, True, 0
+    for i in order:
+        if t_all > budget_s:
+            break
+        t0 = time.perf_counter()
+        s = streams[i]
+        g, T, N = s["geom"], s["n_train"], s["n_test"]
+        train = list(s["train"].cpu().numpy())
+        tests = [s["test"][t].cpu().numpy() for t in (0, N - 1)]
+        t1 = time.perf_counter()
+        f = octree.Forest(g.width, g.height, g.depth)
+        model = f.merge(f.add_frames(train), *s["thr"])
+        masks = [model.classify(x) for x in tests]
+        t_run += time.perf_counter() - t1
+        px += (T + len(tests)) * g.width * g.height
+        ok = ok and bool(np.array_equal(model.leafset(), s["leafset"].cpu().numpy().view(np.uint32)))
+        for t, want in zip((0, N - 1), masks):
+            ok = ok and bool(np.array_equal(want, s["mask"][t].cpu().numpy().view(np.uint64)))
+            fg += int(np.unpackbits(want.view(np.uint8)).sum())
+        checked += 1
+        t_all += time.perf_counter() - t0
+    return {"value": px / t_run / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
+            "sample": f"the {checked} smallest streams of the batched workload: trees of all training frames, "
+                      f"the merge, and test frames 0 and 199, single-threaded, {t_run:.1f} s",
+            "verified": {"streams": checked, "leaf_sets_and_masks_equal": ok, "foreground_bits_compared": fg}}
+
+
+def run_batched(a):
+    out = {"metric": "train+classify Gpixel/s (batched)", "unit": "Gpixel/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u8", "data": "synthetic"}
+    b = batched_leg(a, a.steps, a.warmup, verify_oracle=not a.no_cpu_baseline)
+    out.update({"value": b["gpixel_s"], "ms_per_step": b["ms"],
+                "config": {"workload": b["workload"], "streams": b["streams"], "train_gpx": b["train_gpx"],
+                           "test_gpx": b["test_gpx"]},
+                "batched": b, "roofline": b["roofline"]})
     print(json.dumps(out), flush=True)
 
 
@@ -354,12 +416,13 @@ def oracle_served_replay(spec, depth, T, num, den, n_frames, period, window, bud
     return masks, time.perf_counter() - t0
 
 
-def run_served(a):
+def served_leg(a):
     """Serving: 256 streams of the mixed workload, Poisson arrivals at 5-30 fps
     each, frames written into HBM by the synthetic source when admitted,
     continuous batching under a 32 GiB budget, re-merge every 100 test frames
     over the last 50.  Two runs: real time (latency at the offered load) and
-    every frame offered at once (capacity)."""
+    every frame offered at once (capacity).  Returns the figures as a dict
+    (a full bench line)."""
     import numpy as np
     import torch
     from paper_1412_1945_amd import obg
@@ -483,14 +546,22 @@ def run_served(a):
         got, dt = oracle_served_replay(sp, depths[small], sp.n_train, *thrs[small], n_frames[small],
                                        period, window, budget_s=15.0, region=region)
         ok = bool(wmasks) and all(np.array_equal(wmasks[0][i], got[i]) for i in range(len(got)))
+        fg = sum(int(np.unpackbits(m.view(np.uint8)).sum()) for m in got)
         px = (sp.n_train + len(got)) * sp.width * sp.height
         out["cpu_baseline"] = {"value": px / dt / 1e9, "unit": "Gpixel/s", "cores": 1, "kind": "oracle",
                                "cpu_model": host_cpu()[1],
                                "sample": f"stream {small} ({sp.width}x{sp.height}, d={depths[small]}): "
                                          f"{sp.n_train} training frames and the first {len(got)} served test "
                                          f"frames with re-merges, {dt:.1f} s single-threaded",
-                               "masks_equal_served": bool(ok)}
-    print(json.dumps(out), flush=True)
+                               "masks_equal_served": bool(ok), "test_frames_compared": len(got),
+                               "foreground_bits_compared": fg}
+    del ctx
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_served(a):
+    print(json.dumps(served_leg(a)), flush=True)
 
 
 def main():
@@ -690,10 +761,31 @@ def main():
     if not a.no_cpu_baseline:
         print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
         host_train = list(train.cpu().numpy())
+
+        def classify_with(leaf_host):
+            leaf_dev = torch.from_numpy(np.ascontiguousarray(leaf_host).view(np.int32)).to(dev)
+            mask_f.fill_(-1)
+            obg.obg_classify(g, test, N, leaf_dev, mask_f)
+            torch.cuda.synchronize()
+            return lambda i: mask_f[i].cpu().numpy().view(np.uint64)
+
         out["cpu_baseline"] = cpu_baseline(host_train, lambda i: test[i].cpu().numpy(), N, spec, depth,
                                            num, den, (rw, rh), a.cpu_seconds,
                                            gpu_leaf=leaf.cpu().numpy().view(np.uint32),
-                                           gpu_mask=lambda i: mask[i].cpu().numpy().view(np.uint64))
+                                           gpu_mask=lambda i: mask[i].cpu().numpy().view(np.uint64),
+                                           gpu_classify=classify_with)
+    if a.workload == "plain1080" and not a.no_extra_legs:
+        # the rest of the metric: batched vs plain (64 streams) and served
+        # latency (256 streams), each with its own roofline and oracle check
+        del frames, train, test, occ, leaf, mask, occ_t, mask_f
+        torch.cuda.empty_cache()
+        out["batched"] = batched_leg(a, steps=min(a.steps, 10), warmup=min(a.warmup, 2),
+                                     verify_oracle=not a.no_cpu_baseline)
+        sv = served_leg(a)
+        for k in ("metric", "unit", "n_gpus", "steps", "warmup", "higher_is_better", "scaling", "vs_baseline",
+                  "dtype", "data", "value", "ms_per_step"):
+            sv.pop(k, None)
+        out["served"] = sv
     print(json.dumps(out), flush=True)
 
 

@@ -41,7 +41,7 @@
  * Memory and streams: every buffer pointer is a DEVICE pointer owned by the
  * caller.  Calls validate their arguments, enqueue kernels on `stream`
  * (NULL = the default stream) and return without waiting; the library keeps
- * no pointer after a call returns (except inside an obg_batch, see below).
+ * no pointer after a call returns.
  * Outputs are written completely by the call (no pre-zeroing needed).
  * Faults inside a kernel surface at the caller's next synchronisation.
  *
@@ -170,67 +170,100 @@ int obg_score(const obg_geom *g, const uint64_t *mask, const uint64_t *truth, in
               hipStream_t stream);
 
 /*
- * Batched form: many independent streams of uneven resolution, depth,
- * training length and threshold.  obg_batch_run enqueues the whole batch as
- * three steps, each ONE persistent launch over all streams: the per-frame
- * trees of every training frame (Algorithm 1 + Section 2 pruning), the merge
- * of every stream's trees with its own threshold (Algorithm 2), and the
- * foreground masks of every test frame (Algorithm 3).  The autotuner may
- * instead split the trees and masks steps into one persistent launch per
- * depth present (all streams of that depth; the code of one depth inlined),
- * when that is faster.  The steps are captured once in a HIP graph at
- * creation and replayed.  Outputs are byte-identical
- * to the one-stream calls (obg_train_frame / obg_merge / obg_classify).
+ * Batched form (Algorithms 1-3 over many streams): many independent camera
+ * streams of uneven resolution, depth, training length and threshold in one
+ * persistent launch per step.
  *
- * Each stream: plain geometry (region_w = region_h = 0), depth 1..6,
- * 1 <= n_train <= 65535 training frames merged as one window (threshold
- * thr_num/thr_den as in obg_merge), n_test >= 0 test frames.  Buffers are
- * device pointers owned by the caller and must stay valid while the batch
- * exists; the batch keeps them (and copies of the descriptors).
- *   occ     : out, [n_train][ceil(8^d/32)] uint32 (written by every run)
- *   leafset : out, [ceil(8^d/32)] uint32
- *   mask    : out, [n_test][height][ceil(width/64)] uint64
- * flags: OBG_BATCH_AUTOTUNE times launch shapes on the actual buffers (the
- * call then runs the batch several times and waits for it; every shape is
- * checked to give the same bytes), OBG_BATCH_NO_GRAPH launches the kernels
- * directly on every run instead of a captured graph.  `stream` is used only
- * for those autotuning runs.  Runs of one batch must not overlap.
+ * A plan is made once from host descriptions of its streams (geometry,
+ * depth, threshold, most frames per run).  Each run then takes a DEVICE
+ * array of work items, one per stream that takes part, giving that run's
+ * frames, frame counts and output buffers, so one plan serves new frames,
+ * new buffers and changing counts without being made again.  A run enqueues
+ * on `stream`:
+ *   a prepare kernel (one workgroup) that checks the items, writes each
+ *   item's status, and lays out the run's work in the plan's device memory;
+ *   then the three steps, each ONE persistent launch over all streams (or one
+ *   per depth present, when the autotuner picked that):
+ *     trees of every training frame (Algorithm 1 with the pruning of
+ *     Section 2), the merge of every stream that trained (Algorithm 2, the
+ *     stream's threshold), the masks of every test frame (Algorithm 3).
+ *   The steps read their item counts from device memory, so they are
+ *   captured once in a HIP graph when the plan is made and replayed by every
+ *   run (OBG_TUNE_BATCH_GRAPH = 2 launches them directly instead).
+ * Per stream, the outputs are byte-identical to the one-stream calls:
+ * obg_train_frame over the item's n_train frames, obg_merge of all of them
+ * (window = the n_train trees), and obg_classify of its n_test frames.
+ *
+ * Plan streams: plain geometry (region_w = region_h = 0), depth 1..6,
+ * pitches as for the one-stream calls, thr_num, thr_den >= 1,
+ * 0 <= max_train <= 65535, max_test >= 0; at most 8192 streams.
+ * Work item (device memory, written back only in `status`):
+ *   stream    index of a plan stream; each stream at most once per run
+ *   n_train   0..max_train training frames at train_rgb (the stream's
+ *             frame_pitch apart, 16-byte aligned): their trees are written
+ *             to occ [n_train][ceil(8^d/32)] uint32 and their merge to
+ *             leafset [ceil(8^d/32)] uint32.  n_train = 0: no trees, and
+ *             leafset is the model the test frames are checked against
+ *   n_test    0..max_test test frames at test_rgb: masks to mask
+ *             [n_test][height][ceil(width/64)] uint64
+ *   status    set by the run: OBG_ITEM_OK, or why the item was skipped
+ *             (nothing of a skipped item is written)
+ * A stream that no item names is left alone.  n_items must be in
+ * [0, n_streams] (EINVAL otherwise); n_items = 0 enqueues nothing.  The
+ * library reads the item array on the device during the run: it must stay
+ * valid until the run completes.  Runs of one plan must not overlap (they
+ * share the plan's device memory): issue them on one stream, or order them.
+ *
+ * obg_plan_tune times launch shapes (one launch per phase or per depth;
+ * workgroup size, workgroups per CU, work-item size and dealing of each
+ * step) on the given work, which it runs several times, waiting for each;
+ * every shape must give the same output bytes (else OBG_EHIP); the plan
+ * keeps the fastest and captures its graph again.  It must not overlap a
+ * run of the plan.
  */
-typedef struct obg_stream_desc {
+typedef struct obg_plan_stream {
     obg_geom geom;
-    const uint8_t *train_rgb;
-    int32_t n_train;
     uint32_t thr_num, thr_den;
+    int32_t max_train, max_test;
+} obg_plan_stream;
+
+typedef struct obg_work_item {
+    int32_t stream;
+    int32_t n_train, n_test;
+    int32_t status;
+    const uint8_t *train_rgb;
     const uint8_t *test_rgb;
-    int32_t n_test;
     uint32_t *occ;
     uint32_t *leafset;
     uint64_t *mask;
-} obg_stream_desc;
+} obg_work_item;
 
-typedef struct obg_batch obg_batch;
+#define OBG_ITEM_OK          0
+#define OBG_ITEM_BAD_STREAM  1   /* stream outside the plan                     */
+#define OBG_ITEM_BAD_COUNT   2   /* n_train or n_test outside [0, max]          */
+#define OBG_ITEM_NULL        3   /* a buffer the counts need is NULL            */
+#define OBG_ITEM_ALIGN       4   /* frames not 16-, trees 4-, masks 8-aligned   */
+#define OBG_ITEM_DUPLICATE   5   /* an earlier item of the run names the stream */
 
-#define OBG_BATCH_AUTOTUNE  1u
-#define OBG_BATCH_NO_GRAPH  2u
+typedef struct obg_plan obg_plan;
 
-typedef struct obg_batch_info {
+typedef struct obg_plan_info {
     int32_t n_streams;
-    int64_t train_items, classify_items;      /* work items of each step   */
-    int64_t pixels_train, pixels_test;        /* pixels one run touches    */
+    int64_t max_train_items, max_classify_items;   /* work items of each step at the maxima */
     int32_t train_block, train_wg_per_cu, train_items_per_wg;
     int32_t classify_block, classify_wg_per_cu, classify_span;
-    int32_t graph;                            /* 1: runs replay a graph    */
-    int32_t tune_candidates;                  /* shapes timed (autotune)   */
-    double tune_default_ms, tune_best_ms;     /* one run, default vs chosen */
     int32_t classify_round_robin;             /* 1: classify items dealt round-robin */
     int32_t per_depth_launches;               /* 1: one launch per depth and phase */
-} obg_batch_info;
+    int32_t graph;                            /* 1: runs replay a graph    */
+    int32_t tune_candidates;                  /* shapes timed (obg_plan_tune) */
+    double tune_default_ms, tune_best_ms;     /* one run, first vs chosen shape */
+} obg_plan_info;
 
-int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t flags,
-                     hipStream_t stream, obg_batch **out);
-int obg_batch_run(obg_batch *batch, hipStream_t stream);
-int obg_batch_info_get(const obg_batch *batch, obg_batch_info *out);
-void obg_batch_destroy(obg_batch *batch);
+int obg_plan_create(const obg_plan_stream *streams, int32_t n_streams, obg_plan **out);
+int obg_plan_tune(obg_plan *plan, const obg_work_item *work_items_dev, int32_t n_items, hipStream_t stream);
+int obg_batch_run(obg_plan *plan, const obg_work_item *work_items_dev, int32_t n_items, hipStream_t stream);
+int obg_plan_info_get(const obg_plan *plan, obg_plan_info *out);
+void obg_plan_destroy(obg_plan *plan);
 
 /*
  * Serving: continuous batching of frames that arrive from many cameras.
@@ -315,8 +348,10 @@ typedef struct obg_serve_config {
     /* Checkpoint, NULLABLE (host buffers of obg_serve_state_bytes bytes).
        state_out receives, when the run ends, every stream's merged leaf set,
        its ring of per-frame trees and the index of its next frame (region
-       streams may hold their bitsets in the kernels' own bit order: a state
-       is for restoring, not for reading).  state_in
+       streams may hold their bitsets in the kernels' own bit order, which
+       the stream's record names: a state is for restoring, not for reading;
+       a state restored under an OBG_TUNE_LAYOUT setting that picks the other
+       order for a stream is refused with OBG_EINVAL).  state_in
        restores such a state (written for the same streams: geometry, depth,
        n_train, regions, and the same remerge_window) before the first frame
        is admitted; arrivals[s][i] is then frame next_frame[s] + i, and every
@@ -343,7 +378,7 @@ typedef struct obg_serve_stats {
 int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats);
 /* Bytes of a serving checkpoint of these streams (-1 if a description is
    invalid): a 16-byte header (magic, n_streams, remerge_window), 48 bytes per
-   stream (geometry, ring length, next frame, tree bytes), then per stream its
+   stream (geometry, ring length, bit order, next frame, tree bytes), then per stream its
    leaf set and its ring of trees, each padded to 8 bytes. */
 int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams, int32_t remerge_window);
 
@@ -387,10 +422,12 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
  *                               item per (frame, chunk) whose words are
  *                               stored (default); 2 = chunks only where a
  *                               row's tables do not fit in LDS
- *   OBG_TUNE_BATCH_PER_DEPTH    shape a batch starts from (obg_batch_create,
- *                               before any autotuning): 1 = one persistent
+ *   OBG_TUNE_BATCH_PER_DEPTH    shape a plan starts from (obg_plan_create,
+ *                               before any tuning): 1 = one persistent
  *                               launch per phase (default), 2 = one launch
  *                               per depth present and phase
+ *   OBG_TUNE_BATCH_GRAPH        1 = plans capture their steps in a HIP graph
+ *                               (default), 2 = runs launch them directly
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1
@@ -403,7 +440,8 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
 #define OBG_TUNE_MASK_STAGE          8
 #define OBG_TUNE_REGION_CHUNKS       9
 #define OBG_TUNE_BATCH_PER_DEPTH     10
-#define OBG_TUNE_COUNT               11
+#define OBG_TUNE_BATCH_GRAPH         11
+#define OBG_TUNE_COUNT               12
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 

@@ -205,7 +205,12 @@ class Model:
         return mask
 
     def check_pixel(self, x: int, y: int, r: int, g: int, b: int) -> bool:
-        return bool(self.lib.orc_check_pixel(self.h, x, y, r, g, b))
+        """Check Color (Algorithm 3) of one pixel at (x, y) with colour (r, g, b)
+        against its region's merged tree: True = background."""
+        rc = self.lib.orc_check_pixel(self.h, x, y, r, g, b)
+        if rc < 0:
+            raise IndexError((x, y))
+        return bool(rc)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -607,9 +607,18 @@ int orc_redraw(const Forest *f, int frame, const uint8_t *rgb, int64_t row_pitch
     return 0;
 }
 
-/* Check Color of one pixel (used for sampled checks of very large runs). */
+/* Check Color of one pixel (used for sampled checks of very large runs).
+ * Returns -1 for a pixel outside the frame. */
 int orc_check_pixel(const Model *m, int x, int y, uint8_t r, uint8_t g, uint8_t b) {
+    if (x < 0 || y < 0 || x >= m->g.width || y >= m->g.height) return -1;
+#if ORC_MUTANT == 11  /* one pixel's check: red and blue arguments exchanged */
+    { uint8_t t = r; r = b; b = t; }
+#endif
+#if ORC_MUTANT == 12  /* one pixel's check: region looked up in the transposed grid */
+    const Node *root = m->trees->roots[(x / m->g.region_w) * m->g.reg_rows + y / m->g.region_h];
+#else
     const Node *root = m->trees->roots[region_of(&m->g, x, y)];
+#endif
     return check_color(root, r, g, b, m->g.depth);
 }
 

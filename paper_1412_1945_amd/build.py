@@ -2,6 +2,7 @@
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -22,15 +23,27 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
+def _jobs() -> int:
+    for key in ("MAX_JOBS", "OMP_NUM_THREADS"):
+        try:
+            return max(1, int(os.environ[key]))
+        except (KeyError, ValueError):
+            pass
+    return max(1, min(len(SOURCES), os.cpu_count() or 1))
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-c", os.path.join(CSRC, src), "-o", obj]
+    """Compile every source (in parallel, one hipcc per file) and link."""
+    objs = [os.path.join(CSRC, src.replace(".hip", ".o")) for src in SOURCES]
+
+    def compile_one(i):
+        cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-c", os.path.join(CSRC, SOURCES[i]), "-o", objs[i]]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    with ThreadPoolExecutor(min(_jobs(), len(SOURCES))) as ex:
+        list(ex.map(compile_one, range(len(SOURCES))))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

@@ -1,22 +1,32 @@
-// batch.hip -- many streams of uneven geometry, depth, training length and
-// threshold in one persistent launch per step.
+// batch.hip -- the batched form: one plan over many streams of uneven
+// geometry, depth, training length and threshold, run on work items that the
+// caller passes in device memory.
 //
-// A batch has three steps, each one launch over all streams:
+// A run has three steps, each one persistent launch over all streams (or one
+// per depth present, when the autotuner finds that faster):
 //   train     per-frame trees (occupancy bitsets) of every training frame
 //             (Algorithm 1 with the pruning of Section 2);
 //   merge     the leaf set of every stream from all of its training trees
 //             (Algorithm 2, closed form);
 //   classify  the foreground mask of every test frame (Algorithm 3).
-// Work items are (stream, frame, span of 16-pixel groups); a workgroup takes
-// a contiguous run of items, so it keeps one stream's leaf table in LDS for
-// many items.  The steps (plus the zeroing of the occupancy outputs) are
-// captured once in a HIP graph and replayed by obg_batch_run.
+// The plan fixes each stream's geometry, depth and threshold, and the launch
+// shape.  A run's work items (a device array) name the streams that take
+// part and give their frames, frame counts and output buffers.  A one-block
+// prepare kernel turns the items into the plan's device descriptors: per
+// stream its buffers and counts, the first work item of each step, and the
+// item total of every launch.  The three steps read everything from those
+// descriptors, so they are captured once in a HIP graph at plan creation and
+// the same graph serves every run.
+//
+// Work items of a step are (stream, frame, span of 16-pixel groups); a
+// workgroup takes a contiguous run of them (or every grid-th one), so it
+// keeps one stream's leaf table in LDS for many items.
 #include <stdarg.h>
 #include <stdio.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
-#include <mutex>
 #include <string>
 #include <vector>
 
@@ -27,34 +37,47 @@ namespace obg {
 
 // Largest LDS table of one tree: d = 6 compact (8192 words); d = 5 wide is 7968.
 constexpr int kBatchTableWords = 8192;
+constexpr int kDepthGroups = 6;           // depths 1..6, one group each at most
+constexpr int kPrepareBlock = 1024;
+constexpr int kPlanMaxStreams = 8192;     // claims of one run live in LDS
+// item totals: [2 * g] train and [2 * g + 1] classify items of depth group g,
+// [2 * kDepthGroups (+1)] of all streams
+constexpr int kTotals = 2 * kDepthGroups + 2;
 
 struct BatchStreamDev {
     StripArgs a;              // geometry of the stream's frames (one region)
-    const uint8_t *train_rgb, *test_rgb;
-    uint32_t *occ, *leaf;
-    uint64_t *mask;
-    int32_t depth;
-    int32_t n_train, n_test;
+    // fixed by the plan and its launch shape
+    int32_t stream;           // plan stream held by this slot (slots are sorted by depth)
+    int32_t depth, group;     // depth and index of its depth group
     int32_t groups;           // 16-pixel groups per frame: height * gpr
     int32_t tspans, tspan;    // training frames: items per frame, groups per item
     int32_t cspans, cspan;    // test frames
-    int64_t titem0, citem0;   // the stream's first item in each step
+    int32_t words, valid_bits;
+    uint32_t thr_num, thr_den;
+    int32_t max_train, max_test;
+    // written by the prepare kernel of each run
+    int32_t n_train, n_test;
+    const uint8_t *train_rgb, *test_rgb;
+    uint32_t *occ, *leaf;
+    uint64_t *mask;
+    int64_t titem0, citem0;   // the slot's first item in its launch of each step
     uint32_t kmin;
-    int32_t planes, empty, words, valid_bits;
+    int32_t planes, empty;
 };
 
 struct BatchArgs {
-    const BatchStreamDev *streams;
+    const BatchStreamDev *streams;   // the launch's first slot
     int32_t n_streams;
-    int64_t n_items;
+    const int64_t *n_items;          // the launch's item count, written by the prepare kernel
     int32_t interleave;
     int32_t stage_mask;
 };
 
-// Item `it` belongs to the last stream whose first item is <= it.  A
-// workgroup's next item is nearly always in the stream of its last one
-// (`hint`), which is checked first: the search is a chain of dependent loads
-// that would cost about as much as streaming a small item.
+// Item `it` belongs to the last slot whose first item is <= it (a slot
+// without items has the first item of the next slot, so that slot is never
+// the answer).  A workgroup's next item is nearly always in the slot of its
+// last one (`hint`), which is checked first: the search is a chain of
+// dependent loads that would cost about as much as streaming a small item.
 template <int MODE>
 __device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it, int hint = -1) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
@@ -76,7 +99,9 @@ __device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it, int hin
     return lo;
 }
 
-// Work item `local` of stream sd: the frame and the groups it covers.
+// Work item `local` of stream sd: the frame and the groups it covers.  A
+// training frame that is one item writes its tree with plain stores; frames
+// cut into several items OR their words into a zeroed tree.
 template <int D, int LAY, int MODE, int BLOCK>
 __device__ __forceinline__ void item_body(const BatchArgs &b, const BatchStreamDev &sd, int64_t local,
                                           uint32_t *tab, uint16_t *st_mask, bool new_stream) {
@@ -110,7 +135,32 @@ __device__ __forceinline__ void item_body(const BatchArgs &b, const BatchStreamD
     span_loop<D, MODE, LAY, false, BLOCK>(a, rs, ms, gb, ge, tab, tab, nullptr, stage);
     if (OCC) {
         __syncthreads();
-        occ_from_lds<D, LAY>(tab, sd.occ + (int64_t)f * sd.words, 1, tid, BLOCK);
+        occ_from_lds<D, LAY>(tab, sd.occ + (int64_t)f * sd.words, 1, tid, BLOCK, sd.tspans == 1);
+    }
+}
+
+// The items [i0, i1) (every istep-th) of one launch, the item code of every
+// depth reached through `body`.
+template <int MODE, typename Body>
+__device__ __forceinline__ void walk_items(const BatchArgs &b, Body body) {
+    const int64_t n_items = *b.n_items;
+    int64_t i0, i1, istep;
+    if (b.interleave) {
+        i0 = blockIdx.x;
+        i1 = n_items;
+        istep = gridDim.x;
+    } else {
+        i0 = n_items * blockIdx.x / gridDim.x;
+        i1 = n_items * (blockIdx.x + 1) / gridDim.x;
+        istep = 1;
+    }
+    int cur = -1;
+    for (int64_t it = i0; it < i1; it += istep) {
+        const int s = stream_of<MODE>(b, it, cur);
+        const BatchStreamDev &sd = b.streams[s];
+        const int64_t local = it - ((MODE & MODE_MASK) ? sd.citem0 : sd.titem0);
+        body(sd, local, s != cur);
+        cur = s;
     }
 }
 
@@ -120,7 +170,7 @@ __device__ __forceinline__ void item_body(const BatchArgs &b, const BatchStreamD
 // stack.
 template <int D, int LAY, int MODE, int BLOCK>
 __device__ __attribute__((noinline)) void batch_item(const BatchArgs &b, const BatchStreamDev &sd, int64_t local,
-                                           uint32_t *tab, uint16_t *st_mask, bool new_stream) {
+                                                     uint32_t *tab, uint16_t *st_mask, bool new_stream) {
     item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, new_stream);
 }
 
@@ -132,24 +182,9 @@ __global__ __launch_bounds__(BLOCK) void batch_depth_kernel(BatchArgs b) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     __shared__ uint32_t tab[lds_words(D, LAY)];
     __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
-    int64_t i0, i1, istep;
-    if (b.interleave) {
-        i0 = blockIdx.x;
-        i1 = b.n_items;
-        istep = gridDim.x;
-    } else {
-        i0 = b.n_items * blockIdx.x / gridDim.x;
-        i1 = b.n_items * (blockIdx.x + 1) / gridDim.x;
-        istep = 1;
-    }
-    int cur = -1;
-    for (int64_t it = i0; it < i1; it += istep) {
-        const int s = stream_of<MODE>(b, it, cur);
-        const BatchStreamDev &sd = b.streams[s];
-        const int64_t local = it - (MASK ? sd.citem0 : sd.titem0);
-        item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, s != cur);
-        cur = s;
-    }
+    walk_items<MODE>(b, [&](const BatchStreamDev &sd, int64_t local, bool fresh) {
+        item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh);
+    });
 }
 
 template <int MODE, int BLOCK>
@@ -157,22 +192,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs b) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     __shared__ uint32_t tab[kBatchTableWords];
     __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
-    int64_t i0, i1, istep;
-    if (b.interleave) {
-        i0 = blockIdx.x;
-        i1 = b.n_items;
-        istep = gridDim.x;
-    } else {
-        i0 = b.n_items * blockIdx.x / gridDim.x;
-        i1 = b.n_items * (blockIdx.x + 1) / gridDim.x;
-        istep = 1;
-    }
-    int cur = -1;
-    for (int64_t it = i0; it < i1; it += istep) {
-        const int s = stream_of<MODE>(b, it, cur);
-        const BatchStreamDev &sd = b.streams[s];
-        const int64_t local = it - (MASK ? sd.citem0 : sd.titem0);
-        const bool fresh = s != cur;
+    walk_items<MODE>(b, [&](const BatchStreamDev &sd, int64_t local, bool fresh) {
         switch (sd.depth) {
             case 1: batch_item<1, LAY_WIDE, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh); break;
             case 2: batch_item<2, LAY_WIDE, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh); break;
@@ -181,31 +201,161 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs b) {
             case 5: batch_item<5, LAY_WIDE, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh); break;
             default: batch_item<6, LAY_COMPACT, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh); break;
         }
-        cur = s;
-    }
+    });
 }
 
-// Merge of every stream: block row y = stream, one thread per 32 keys.
+// Merge of every stream that trained in this run: block row y = slot, one
+// thread per 32 keys.
 __global__ __launch_bounds__(256) void batch_merge_kernel(const BatchStreamDev *streams) {
     const BatchStreamDev &sd = streams[blockIdx.y];
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= sd.words) return;
+    if (sd.n_train < 1 || i >= sd.words) return;
     sd.leaf[i] = merge_word(sd.occ, sd.n_train, 0, sd.n_train, sd.words, i, sd.valid_bits, sd.kmin,
                             sd.planes, sd.empty);
 }
 
-// Zero every stream's occupancy output (block row y = stream).
+// Zero the trees of training frames cut into several items (block row y =
+// slot); single-item frames store their trees whole.
 __global__ __launch_bounds__(256) void batch_zero_kernel(const BatchStreamDev *streams) {
     const BatchStreamDev &sd = streams[blockIdx.y];
+    if (sd.tspans < 2) return;
     const int64_t n = (int64_t)sd.n_train * sd.words;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         sd.occ[i] = 0;
 }
 
-// Order-independent checksum of every output word (autotuner cross-check).
-// Each word is mixed with its stream, its kind and its position before a
-// non-linear finaliser, so a word written to the wrong place (or the wrong
-// stream) changes the sum.
+// ---------------------------------------------------------------------------
+// The prepare kernel: one workgroup turns a run's work items into the slots'
+// per-run fields and the launches' item counts.
+
+struct PrepareArgs {
+    BatchStreamDev *d;
+    int32_t n;                 // slots (= plan streams)
+    const int32_t *slot_of;    // plan stream -> slot
+    int64_t *totals;           // [kTotals]
+    int32_t per_depth;         // items numbered per depth group (one launch per depth)
+    int32_t n_groups;
+};
+
+__device__ __forceinline__ int item_check(const obg_work_item &it, const BatchStreamDev *d, const int32_t *slot_of,
+                                          int n) {
+    if (it.stream < 0 || it.stream >= n) return OBG_ITEM_BAD_STREAM;
+    const BatchStreamDev &s = d[slot_of[it.stream]];
+    if (it.n_train < 0 || it.n_train > s.max_train || it.n_test < 0 || it.n_test > s.max_test)
+        return OBG_ITEM_BAD_COUNT;
+    if (it.n_train == 0 && it.n_test == 0) return OBG_ITEM_OK;
+    if (!it.leafset || (it.n_train > 0 && (!it.train_rgb || !it.occ)) || (it.n_test > 0 && (!it.test_rgb || !it.mask)))
+        return OBG_ITEM_NULL;
+    const uintptr_t a16 = (it.n_train > 0 ? (uintptr_t)it.train_rgb : 0) | (it.n_test > 0 ? (uintptr_t)it.test_rgb : 0);
+    const uintptr_t a4 = (uintptr_t)it.leafset | (it.n_train > 0 ? (uintptr_t)it.occ : 0);
+    const uintptr_t a8 = it.n_test > 0 ? (uintptr_t)it.mask : 0;
+    if ((a16 & 15) || (a4 & 3) || (a8 & 7)) return OBG_ITEM_ALIGN;
+    return OBG_ITEM_OK;
+}
+
+__global__ __launch_bounds__(kPrepareBlock) void plan_prepare_kernel(PrepareArgs p, obg_work_item *items,
+                                                                      int32_t n_items) {
+    __shared__ int32_t claim[kPlanMaxStreams];
+    __shared__ int64_t sc_t[kPrepareBlock], sc_c[kPrepareBlock];
+    __shared__ int64_t g0_t[kDepthGroups + 1], g0_c[kDepthGroups + 1];
+    const int tid = threadIdx.x;
+    for (int s = tid; s < p.n; s += kPrepareBlock) {
+        p.d[s].n_train = 0;
+        p.d[s].n_test = 0;
+        claim[s] = INT_MAX;
+    }
+    __syncthreads();
+    // each stream is taken by the first item that names it
+    for (int i = tid; i < n_items; i += kPrepareBlock) {
+        const obg_work_item it = items[i];
+        if (item_check(it, p.d, p.slot_of, p.n) == OBG_ITEM_OK) atomicMin(&claim[p.slot_of[it.stream]], i);
+    }
+    __syncthreads();
+    for (int i = tid; i < n_items; i += kPrepareBlock) {
+        const obg_work_item it = items[i];
+        int st = item_check(it, p.d, p.slot_of, p.n);
+        if (st == OBG_ITEM_OK) {
+            const int slot = p.slot_of[it.stream];
+            if (claim[slot] != i) {
+                st = OBG_ITEM_DUPLICATE;
+            } else {
+                BatchStreamDev &sd = p.d[slot];
+                sd.n_train = it.n_train;
+                sd.n_test = it.n_test;
+                sd.train_rgb = it.train_rgb;
+                sd.test_rgb = it.test_rgb;
+                sd.occ = it.occ;
+                sd.leaf = it.leafset;
+                sd.mask = it.mask;
+                // keep a key iff count * den >= num * n_train: the smallest such count
+                const uint64_t need = (uint64_t)sd.thr_num * (uint64_t)it.n_train;
+                const uint64_t kmin = (need + sd.thr_den - 1) / sd.thr_den;
+                sd.empty = kmin > (uint64_t)it.n_train ? 1 : 0;
+                sd.kmin = sd.empty ? 0u : (uint32_t)kmin;
+                int planes = 0;
+                while ((1 << planes) <= it.n_train) ++planes;
+                sd.planes = planes;
+            }
+        }
+        items[i].status = st;
+    }
+    __syncthreads();
+    // first items: a scan over the slots (each thread a contiguous chunk)
+    const int ch = (p.n + kPrepareBlock - 1) / kPrepareBlock;
+    const int s0 = min(p.n, tid * ch), s1 = min(p.n, s0 + ch);
+    int64_t lt = 0, lc = 0;
+    for (int s = s0; s < s1; ++s) {
+        lt += (int64_t)p.d[s].tspans * p.d[s].n_train;
+        lc += (int64_t)p.d[s].cspans * p.d[s].n_test;
+    }
+    sc_t[tid] = lt;
+    sc_c[tid] = lc;
+    __syncthreads();
+    for (int off = 1; off < kPrepareBlock; off <<= 1) {
+        const int64_t vt = tid >= off ? sc_t[tid - off] : 0;
+        const int64_t vc = tid >= off ? sc_c[tid - off] : 0;
+        __syncthreads();
+        sc_t[tid] += vt;
+        sc_c[tid] += vc;
+        __syncthreads();
+    }
+    int64_t rt = sc_t[tid] - lt, rc = sc_c[tid] - lc;
+    for (int s = s0; s < s1; ++s) {
+        BatchStreamDev &sd = p.d[s];
+        sd.titem0 = rt;
+        sd.citem0 = rc;
+        if (s == 0 || p.d[s - 1].group != sd.group) {
+            g0_t[sd.group] = rt;
+            g0_c[sd.group] = rc;
+        }
+        rt += (int64_t)sd.tspans * sd.n_train;
+        rc += (int64_t)sd.cspans * sd.n_test;
+    }
+    if (tid == 0) {
+        g0_t[p.n_groups] = sc_t[kPrepareBlock - 1];
+        g0_c[p.n_groups] = sc_c[kPrepareBlock - 1];
+    }
+    __syncthreads();
+    if (p.per_depth) {
+        for (int s = s0; s < s1; ++s) {
+            p.d[s].titem0 -= g0_t[p.d[s].group];
+            p.d[s].citem0 -= g0_c[p.d[s].group];
+        }
+    }
+    if (tid < p.n_groups) {
+        p.totals[2 * tid] = g0_t[tid + 1] - g0_t[tid];
+        p.totals[2 * tid + 1] = g0_c[tid + 1] - g0_c[tid];
+    }
+    if (tid == 0) {
+        p.totals[2 * kDepthGroups] = g0_t[p.n_groups];
+        p.totals[2 * kDepthGroups + 1] = g0_c[p.n_groups];
+    }
+}
+
+// Order-independent checksum of every output word of a run (autotuner
+// cross-check).  Each word is mixed with its stream, its kind and its
+// position before a non-linear finaliser, so a word written to the wrong
+// place (or the wrong stream) changes the sum.
 __device__ __forceinline__ unsigned long long check_mix(uint64_t word, uint64_t where) {
     uint64_t x = word ^ (where * 0x9E3779B97F4A7C15ull);
     x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -217,13 +367,14 @@ __global__ __launch_bounds__(256) void batch_checksum_kernel(const BatchStreamDe
     const BatchStreamDev &sd = streams[blockIdx.y];
     const int64_t nm = (int64_t)sd.n_test * sd.a.height * sd.a.mask_row_words;
     const int64_t no = (int64_t)sd.n_train * sd.words;
-    const uint64_t base = (uint64_t)blockIdx.y << 42;   // stream; kind in bits 40..41
+    const int64_t nl = sd.n_train > 0 ? sd.words : 0;
+    const uint64_t base = (uint64_t)sd.stream << 42;   // stream; kind in bits 40..41
     unsigned long long h = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nm; i += (int64_t)gridDim.x * blockDim.x)
         h += check_mix(sd.mask[i], base + (uint64_t)i);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < no; i += (int64_t)gridDim.x * blockDim.x)
         h += check_mix(sd.occ[i], base + (1ull << 40) + (uint64_t)i);
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < sd.words; i += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nl; i += (int64_t)gridDim.x * blockDim.x)
         h += check_mix(sd.leaf[i], base + (2ull << 40) + (uint64_t)i);
     atomicAdd(out, h);
 }
@@ -250,25 +401,26 @@ struct Shape {
     int per_depth;            // 1: one launch per depth and phase, 0: one launch per phase
 };
 
-// Streams of one depth: [s0, s1) of the (depth-sorted) descriptors.
+// Streams of one depth: slots [s0, s1).
 struct DepthGroup {
     int depth, s0, s1;
-    int64_t train_items, classify_items;   // with per-depth launches
+    int64_t max_train_items, max_classify_items;   // when every stream runs its maxima
 };
 
 }  // namespace
 
-struct obg_batch {
+struct obg_plan {
     int device = 0;
     int n_streams = 0;
     int cus = 256;
-    std::vector<obg_stream_desc> desc;
-    std::vector<BatchStreamDev> h;        // sorted by depth
+    std::vector<BatchStreamDev> h;        // slots, sorted by depth
+    std::vector<int32_t> slot_of;         // plan stream -> slot
     std::vector<DepthGroup> groups;
     BatchStreamDev *d = nullptr;
+    int32_t *d_slot_of = nullptr;
+    int64_t *d_totals = nullptr;
     unsigned long long *d_sum = nullptr;
-    int64_t train_items = 0, classify_items = 0;
-    int64_t px_train = 0, px_test = 0;
+    int64_t max_train_items = 0, max_classify_items = 0;
     int max_words = 0;
     Shape shape{};
     bool use_graph = false;
@@ -281,62 +433,55 @@ struct obg_batch {
 
 namespace {
 
-// Split every frame into work items for the current shape and upload the
-// descriptors.
-int plan_items(obg_batch *b) {
+// Split every stream's frames into work items for the current shape and
+// upload the slots (their per-run fields are the prepare kernel's).
+int plan_items(obg_plan *p) {
     int64_t tgroups = 0;
-    for (const auto &h : b->h) tgroups += (int64_t)h.groups * h.n_train;
-    const int64_t train_wgs = (int64_t)b->cus * b->shape.train_wpc;
-    // training items: about train_items_per_wg per workgroup, whole frames
-    // when they are small enough (one LDS flush per item)
-    int64_t tspan_target = tgroups / std::max<int64_t>(1, train_wgs * b->shape.train_items_per_wg);
+    for (const auto &h : p->h) tgroups += (int64_t)h.groups * h.max_train;
+    const int64_t train_wgs = (int64_t)p->cus * p->shape.train_wpc;
+    // training items: about train_items_per_wg per workgroup when every
+    // stream trains on its most frames, whole frames when they are small
+    // enough (one LDS flush per item)
+    int64_t tspan_target = tgroups / std::max<int64_t>(1, train_wgs * p->shape.train_items_per_wg);
     tspan_target = std::max<int64_t>(tspan_target, 4096);
-    // item numbers run over all streams (one launch per phase) or restart at
-    // each depth group (one launch per depth)
-    int64_t t0 = 0, c0 = 0, tt = 0, ct = 0;
-    for (auto &gr : b->groups) {
-        if (b->shape.per_depth) t0 = c0 = 0;
-        const int64_t gt = t0, gc = c0;
+    p->max_train_items = p->max_classify_items = 0;
+    for (auto &gr : p->groups) {
+        gr.max_train_items = gr.max_classify_items = 0;
         for (int s = gr.s0; s < gr.s1; ++s) {
-            BatchStreamDev &h = b->h[s];
+            BatchStreamDev &h = p->h[s];
             int64_t ts = (std::min<int64_t>(tspan_target, h.groups) + 3) & ~int64_t(3);
             h.tspans = (int32_t)((h.groups + ts - 1) / ts);
             h.tspan = (int32_t)((((h.groups + h.tspans - 1) / h.tspans) + 3) & ~3);
-            int64_t cs = (std::min<int64_t>(b->shape.classify_span, h.groups) + 3) & ~int64_t(3);
+            int64_t cs = (std::min<int64_t>(p->shape.classify_span, h.groups) + 3) & ~int64_t(3);
             h.cspans = (int32_t)((h.groups + cs - 1) / cs);
             h.cspan = (int32_t)((((h.groups + h.cspans - 1) / h.cspans) + 3) & ~3);
-            h.titem0 = t0;
-            h.citem0 = c0;
-            t0 += (int64_t)h.tspans * h.n_train;
-            c0 += (int64_t)h.cspans * h.n_test;
+            gr.max_train_items += (int64_t)h.tspans * h.max_train;
+            gr.max_classify_items += (int64_t)h.cspans * h.max_test;
         }
-        gr.train_items = t0 - gt;
-        gr.classify_items = c0 - gc;
-        tt += gr.train_items;
-        ct += gr.classify_items;
+        p->max_train_items += gr.max_train_items;
+        p->max_classify_items += gr.max_classify_items;
     }
-    b->train_items = tt;
-    b->classify_items = ct;
-    hipError_t e = hipMemcpy(b->d, b->h.data(), sizeof(BatchStreamDev) * b->h.size(), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(p->d, p->h.data(), sizeof(BatchStreamDev) * p->h.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bfail(OBG_EHIP, "descriptor upload: %s", hipGetErrorString(e));
     return OBG_OK;
 }
 
 template <int D, int LAY>
-hipError_t launch_depth(obg_batch *b, const DepthGroup &gr, bool train, hipStream_t st) {
-    const Shape &sh = b->shape;
-    const BatchStreamDev *d = b->d + gr.s0;
+hipError_t launch_depth(obg_plan *p, int g, bool train, hipStream_t st) {
+    const Shape &sh = p->shape;
+    const DepthGroup &gr = p->groups[g];
+    const BatchStreamDev *d = p->d + gr.s0;
     const int n = gr.s1 - gr.s0;
     if (train) {
-        BatchArgs a{d, n, gr.train_items, 0, 0};
-        const int grid = (int)std::min<int64_t>(gr.train_items, (int64_t)b->cus * sh.train_wpc);
+        BatchArgs a{d, n, p->d_totals + 2 * g, 0, 0};
+        const int grid = (int)std::min<int64_t>(gr.max_train_items, (int64_t)p->cus * sh.train_wpc);
         if (sh.train_block == 1024)
             hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_OCC, 1024>), dim3(grid), dim3(1024), 0, st, a);
         else
             hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_OCC, 256>), dim3(grid), dim3(256), 0, st, a);
     } else {
-        BatchArgs a{d, n, gr.classify_items, sh.classify_rr, sh.classify_span <= kStageGroups ? 1 : 0};
-        const int grid = (int)std::min<int64_t>(gr.classify_items, (int64_t)b->cus * sh.classify_wpc);
+        BatchArgs a{d, n, p->d_totals + 2 * g + 1, sh.classify_rr, sh.classify_span <= kStageGroups ? 1 : 0};
+        const int grid = (int)std::min<int64_t>(gr.max_classify_items, (int64_t)p->cus * sh.classify_wpc);
         if (sh.classify_block == 512)
             hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_MASK, 512>), dim3(grid), dim3(512), 0, st, a);
         else
@@ -346,56 +491,59 @@ hipError_t launch_depth(obg_batch *b, const DepthGroup &gr, bool train, hipStrea
 }
 
 // One launch per depth group of the phase (train or classify).
-hipError_t enqueue_depths(obg_batch *b, bool train, hipStream_t st) {
-    for (const DepthGroup &gr : b->groups) {
-        if ((train ? gr.train_items : gr.classify_items) <= 0) continue;
+hipError_t enqueue_depths(obg_plan *p, bool train, hipStream_t st) {
+    for (int g = 0; g < (int)p->groups.size(); ++g) {
+        const DepthGroup &gr = p->groups[g];
+        if ((train ? gr.max_train_items : gr.max_classify_items) <= 0) continue;
         hipError_t e;
         switch (gr.depth) {
-            case 1: e = launch_depth<1, LAY_WIDE>(b, gr, train, st); break;
-            case 2: e = launch_depth<2, LAY_WIDE>(b, gr, train, st); break;
-            case 3: e = launch_depth<3, LAY_WIDE>(b, gr, train, st); break;
-            case 4: e = launch_depth<4, LAY_WIDE>(b, gr, train, st); break;
-            case 5: e = launch_depth<5, LAY_WIDE>(b, gr, train, st); break;
-            default: e = launch_depth<6, LAY_COMPACT>(b, gr, train, st); break;
+            case 1: e = launch_depth<1, LAY_WIDE>(p, g, train, st); break;
+            case 2: e = launch_depth<2, LAY_WIDE>(p, g, train, st); break;
+            case 3: e = launch_depth<3, LAY_WIDE>(p, g, train, st); break;
+            case 4: e = launch_depth<4, LAY_WIDE>(p, g, train, st); break;
+            case 5: e = launch_depth<5, LAY_WIDE>(p, g, train, st); break;
+            default: e = launch_depth<6, LAY_COMPACT>(p, g, train, st); break;
         }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-hipError_t enqueue(obg_batch *b, hipStream_t st) {
-    const int ny = b->n_streams;
-    hipLaunchKernelGGL(batch_zero_kernel, dim3(64, ny), dim3(256), 0, st, (const BatchStreamDev *)b->d);
+// The three steps of a run (what the graph holds); they read the slots and
+// item counts the prepare kernel wrote.
+hipError_t enqueue_steps(obg_plan *p, hipStream_t st) {
+    const int ny = p->n_streams;
+    hipLaunchKernelGGL(batch_zero_kernel, dim3(64, ny), dim3(256), 0, st, (const BatchStreamDev *)p->d);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (b->shape.per_depth) {
-        if ((e = enqueue_depths(b, true, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(batch_merge_kernel, dim3((b->max_words + 255) / 256, ny), dim3(256), 0, st,
-                           (const BatchStreamDev *)b->d);
+    if (p->shape.per_depth) {
+        if ((e = enqueue_depths(p, true, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(batch_merge_kernel, dim3((p->max_words + 255) / 256, ny), dim3(256), 0, st,
+                           (const BatchStreamDev *)p->d);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        return enqueue_depths(b, false, st);
+        return enqueue_depths(p, false, st);
     }
-    if (b->train_items > 0) {
-        BatchArgs a{b->d, ny, b->train_items, 0, 0};
-        const int grid = (int)std::min<int64_t>(b->train_items, (int64_t)b->cus * b->shape.train_wpc);
-        if (b->shape.train_block == 1024)
+    if (p->max_train_items > 0) {
+        BatchArgs a{p->d, ny, p->d_totals + 2 * kDepthGroups, 0, 0};
+        const int grid = (int)std::min<int64_t>(p->max_train_items, (int64_t)p->cus * p->shape.train_wpc);
+        if (p->shape.train_block == 1024)
             hipLaunchKernelGGL((batch_kernel<MODE_OCC, 1024>), dim3(grid), dim3(1024), 0, st, a);
         else
             hipLaunchKernelGGL((batch_kernel<MODE_OCC, 256>), dim3(grid), dim3(256), 0, st, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(batch_merge_kernel, dim3((b->max_words + 255) / 256, ny), dim3(256), 0, st,
-                       (const BatchStreamDev *)b->d);
+    hipLaunchKernelGGL(batch_merge_kernel, dim3((p->max_words + 255) / 256, ny), dim3(256), 0, st,
+                       (const BatchStreamDev *)p->d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (b->classify_items > 0) {
+    if (p->max_classify_items > 0) {
         // round-robin: the items in flight at any moment are neighbours in
         // memory, and items are numbered stream by stream, so a workgroup
         // reloads a leaf table only where its items cross into the next
         // stream; contiguous runs meet each stream's table once
-        BatchArgs a{b->d, ny, b->classify_items, b->shape.classify_rr,
-                    b->shape.classify_span <= kStageGroups ? 1 : 0};
-        const int grid = (int)std::min<int64_t>(b->classify_items, (int64_t)b->cus * b->shape.classify_wpc);
-        if (b->shape.classify_block == 512)
+        BatchArgs a{p->d, ny, p->d_totals + 2 * kDepthGroups + 1, p->shape.classify_rr,
+                    p->shape.classify_span <= kStageGroups ? 1 : 0};
+        const int grid = (int)std::min<int64_t>(p->max_classify_items, (int64_t)p->cus * p->shape.classify_wpc);
+        if (p->shape.classify_block == 512)
             hipLaunchKernelGGL((batch_kernel<MODE_MASK, 512>), dim3(grid), dim3(512), 0, st, a);
         else
             hipLaunchKernelGGL((batch_kernel<MODE_MASK, 256>), dim3(grid), dim3(256), 0, st, a);
@@ -404,59 +552,66 @@ hipError_t enqueue(obg_batch *b, hipStream_t st) {
     return hipSuccess;
 }
 
-void drop_graph(obg_batch *b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
+hipError_t enqueue_prepare(obg_plan *p, const obg_work_item *items, int32_t n_items, hipStream_t st) {
+    PrepareArgs a{p->d, p->n_streams, p->d_slot_of, p->d_totals, p->shape.per_depth, (int32_t)p->groups.size()};
+    hipLaunchKernelGGL(plan_prepare_kernel, dim3(1), dim3(kPrepareBlock), 0, st, a,
+                       const_cast<obg_work_item *>(items), n_items);
+    return hipGetLastError();
 }
 
-int build_graph(obg_batch *b) {
-    drop_graph(b);
-    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+void drop_graph(obg_plan *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+}
+
+int build_graph(obg_plan *p) {
+    drop_graph(p);
+    hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bfail(OBG_EHIP, "begin capture: %s", hipGetErrorString(e));
-    hipError_t le = enqueue(b, b->cap);
-    e = hipStreamEndCapture(b->cap, &b->graph);
+    hipError_t le = enqueue_steps(p, p->cap);
+    e = hipStreamEndCapture(p->cap, &p->graph);
     if (le != hipSuccess) return bfail(OBG_EHIP, "launch during capture: %s", hipGetErrorString(le));
     if (e != hipSuccess) return bfail(OBG_EHIP, "end capture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return bfail(OBG_EHIP, "graph instantiate: %s", hipGetErrorString(e));
     return OBG_OK;
 }
 
-int run_once(obg_batch *b, hipStream_t st) {
-    hipError_t e;
-    if (b->use_graph && b->exec)
-        e = hipGraphLaunch(b->exec, st);
-    else
-        e = enqueue(b, st);
+int run_once(obg_plan *p, const obg_work_item *items, int32_t n_items, hipStream_t st, bool graph) {
+    hipError_t e = enqueue_prepare(p, items, n_items, st);
+    if (e == hipSuccess) e = (graph && p->exec) ? hipGraphLaunch(p->exec, st) : enqueue_steps(p, st);
     if (e != hipSuccess) return bfail(OBG_EHIP, "batch launch: %s", hipGetErrorString(e));
     return OBG_OK;
 }
 
-int checksum(obg_batch *b, hipStream_t st, unsigned long long *out) {
-    hipError_t e = hipMemsetAsync(b->d_sum, 0, sizeof(unsigned long long), st);
+int checksum(obg_plan *p, hipStream_t st, unsigned long long *out) {
+    hipError_t e = hipMemsetAsync(p->d_sum, 0, sizeof(unsigned long long), st);
     if (e != hipSuccess) return bfail(OBG_EHIP, "checksum: %s", hipGetErrorString(e));
-    hipLaunchKernelGGL(batch_checksum_kernel, dim3(256, b->n_streams), dim3(256), 0, st,
-                       (const BatchStreamDev *)b->d, b->d_sum);
+    hipLaunchKernelGGL(batch_checksum_kernel, dim3(256, p->n_streams), dim3(256), 0, st,
+                       (const BatchStreamDev *)p->d, p->d_sum);
     if ((e = hipGetLastError()) != hipSuccess) return bfail(OBG_EHIP, "checksum: %s", hipGetErrorString(e));
-    e = hipMemcpyAsync(out, b->d_sum, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    e = hipMemcpyAsync(out, p->d_sum, sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return bfail(OBG_EHIP, "checksum: %s", hipGetErrorString(e));
     return OBG_OK;
 }
 
-int time_shape(obg_batch *b, hipStream_t st, float *ms) {
-    int rc = plan_items(b);
+int time_shape(obg_plan *p, const obg_work_item *items, int32_t n_items, hipStream_t st, float *ms) {
+    int rc = plan_items(p);
     if (rc) return rc;
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (hipEventCreate(&e0) != hipSuccess) return bfail(OBG_EHIP, "event create");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
         return bfail(OBG_EHIP, "event create");
-    rc = run_once(b, st);  // warm-up
+    }
+    rc = run_once(p, items, n_items, st, false);  // warm-up
     float best = 1e30f;
     for (int r = 0; r < 3 && rc == OBG_OK; ++r) {
         (void)hipEventRecord(e0, st);
-        rc = run_once(b, st);
+        rc = run_once(p, items, n_items, st, false);
         (void)hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess) rc = bfail(OBG_EHIP, "timing sync");
         float t = 0;
@@ -469,28 +624,38 @@ int time_shape(obg_batch *b, hipStream_t st, float *ms) {
     return rc;
 }
 
-int autotune(obg_batch *b, hipStream_t st) {
-    const Shape base = b->shape;
+// Time the candidate shapes on the given work, keep the fastest.  Every
+// candidate's outputs must hash to the first shape's.
+int autotune(obg_plan *p, const obg_work_item *items, int32_t n_items, hipStream_t st) {
+    const Shape base = p->shape;
     float best_ms = 0;
-    int rc = time_shape(b, st, &best_ms);
+    int rc = time_shape(p, items, n_items, st, &best_ms);
     if (rc) return rc;
     unsigned long long ref = 0;
-    if ((rc = checksum(b, st, &ref))) return rc;
-    b->tune_default_ms = best_ms;
+    if ((rc = checksum(p, st, &ref))) return rc;
+    p->tune_default_ms = best_ms;
     Shape best = base;
     int n = 0;
+    auto trial = [&](const Shape &s) -> int {
+        p->shape = s;
+        float ms = 0;
+        int r = time_shape(p, items, n_items, st, &ms);
+        if (r) return r;
+        unsigned long long h = 0;
+        if ((r = checksum(p, st, &h))) return r;
+        if (h != ref) return bfail(OBG_EHIP, "autotune: shape gives different output (internal error)");
+        ++n;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = s;
+        }
+        return OBG_OK;
+    };
     // one launch per phase or per depth and phase, with the default shape
     {
         Shape s = best;
         s.per_depth = !base.per_depth;
-        b->shape = s;
-        float ms = 0;
-        if ((rc = time_shape(b, st, &ms))) return rc;
-        unsigned long long h = 0;
-        if ((rc = checksum(b, st, &h))) return rc;
-        if (h != ref) return bfail(OBG_EHIP, "autotune: shape gives different output (internal error)");
-        ++n;
-        if (ms < best_ms) { best_ms = ms; best = s; }
+        if ((rc = trial(s))) return rc;
     }
     const int cblocks[] = {256, 512}, cwpcs[] = {1, 2, 4}, cspans[] = {256, 512, 832, 1024, 4096};
     const int tblocks[] = {256, 1024}, twpcs[] = {1, 2, 4}, titems[] = {1, 4};
@@ -498,85 +663,83 @@ int autotune(obg_batch *b, hipStream_t st) {
         for (int cw : cwpcs)
             for (int cs : cspans)
                 for (int rr = 0; rr < 2; ++rr) {
-                    Shape s = best;
-                    s.classify_block = cb; s.classify_wpc = cw; s.classify_span = cs; s.classify_rr = rr;
                     if (cb == 512 && cw > 2) continue;   // 32 waves per CU at most
-                    b->shape = s;
-                    float ms = 0;
-                    if ((rc = time_shape(b, st, &ms))) return rc;
-                    unsigned long long h = 0;
-                    if ((rc = checksum(b, st, &h))) return rc;
-                    if (h != ref) return bfail(OBG_EHIP, "autotune: shape gives different output (internal error)");
-                    ++n;
-                    if (ms < best_ms) { best_ms = ms; best = s; }
+                    Shape s = best;
+                    s.classify_block = cb;
+                    s.classify_wpc = cw;
+                    s.classify_span = cs;
+                    s.classify_rr = rr;
+                    if ((rc = trial(s))) return rc;
                 }
     for (int tb : tblocks)
         for (int tw : twpcs)
             for (int ti : titems) {
-                Shape s = best;
-                s.train_block = tb; s.train_wpc = tw; s.train_items_per_wg = ti;
                 if (tb == 1024 && tw > 2) continue;
-                b->shape = s;
-                float ms = 0;
-                if ((rc = time_shape(b, st, &ms))) return rc;
-                unsigned long long h = 0;
-                if ((rc = checksum(b, st, &h))) return rc;
-                if (h != ref) return bfail(OBG_EHIP, "autotune: shape gives different output (internal error)");
-                ++n;
-                if (ms < best_ms) { best_ms = ms; best = s; }
+                Shape s = best;
+                s.train_block = tb;
+                s.train_wpc = tw;
+                s.train_items_per_wg = ti;
+                if ((rc = trial(s))) return rc;
             }
-    b->shape = best;
-    b->tune_best_ms = best_ms;
-    b->tune_candidates = n;
-    return plan_items(b);
+    p->shape = best;
+    p->tune_best_ms = best_ms;
+    p->tune_candidates = n;
+    return plan_items(p);
 }
 
-void destroy(obg_batch *b) {
-    if (!b) return;
-    drop_graph(b);
-    if (b->cap) (void)hipStreamDestroy(b->cap);
-    if (b->d) (void)hipFree(b->d);
-    if (b->d_sum) (void)hipFree(b->d_sum);
-    delete b;
+void destroy(obg_plan *p) {
+    if (!p) return;
+    drop_graph(p);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->d) (void)hipFree(p->d);
+    if (p->d_slot_of) (void)hipFree(p->d_slot_of);
+    if (p->d_totals) (void)hipFree(p->d_totals);
+    if (p->d_sum) (void)hipFree(p->d_sum);
+    delete p;
+}
+
+int check_run_args(const obg_plan *p, const obg_work_item *items, int32_t n_items) {
+    if (!p) return bfail(OBG_EINVAL, "plan is NULL");
+    if (n_items < 0 || n_items > p->n_streams)
+        return bfail(OBG_EINVAL, "n_items must be in [0, n_streams = %d] (got %d)", p->n_streams, n_items);
+    if (n_items > 0 && !items) return bfail(OBG_EINVAL, "work items are NULL");
+    if ((uintptr_t)items % 8) return bfail(OBG_EALIGN, "work items must be 8-byte aligned");
+    return OBG_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t flags, hipStream_t stream,
-                     obg_batch **out) {
+int obg_plan_create(const obg_plan_stream *streams, int32_t n_streams, obg_plan **out) {
     if (!out) return bfail(OBG_EINVAL, "out is NULL");
     *out = nullptr;
     if (!streams || n_streams < 1) return bfail(OBG_EINVAL, "need at least one stream");
-    if (flags & ~(uint32_t)(OBG_BATCH_AUTOTUNE | OBG_BATCH_NO_GRAPH)) return bfail(OBG_EINVAL, "unknown flags");
-    obg_batch *b = new obg_batch();
-    b->n_streams = n_streams;
-    b->desc.assign(streams, streams + n_streams);
+    if (n_streams > kPlanMaxStreams) return bfail(OBG_EINVAL, "at most %d streams per plan", kPlanMaxStreams);
+    obg_plan *p = new obg_plan();
+    p->n_streams = n_streams;
     for (int s = 0; s < n_streams; ++s) {
-        const obg_stream_desc &sd = streams[s];
-        const obg_geom &g = sd.geom;
-        if (g.width < 1 || g.height < 1 || g.depth < 1 || g.depth > 6) {
-            destroy(b);
-            return bfail(OBG_EINVAL, "stream %d: width, height >= 1 and depth in [1, 6] required", s);
-        }
-        if (g.region_w || g.region_h) { destroy(b); return bfail(OBG_EINVAL, "stream %d: regions are not batched", s); }
-        if (g.row_pitch < 3LL * g.width || g.frame_pitch < (int64_t)g.height * g.row_pitch || g.frame_pitch > 0x7FFFFFFFLL) {
-            destroy(b);
-            return bfail(OBG_EINVAL, "stream %d: bad pitches", s);
-        }
-        if (g.row_pitch % 16 || g.frame_pitch % 16 || (uintptr_t)sd.train_rgb % 16 || (uintptr_t)sd.test_rgb % 16) {
-            destroy(b);
-            return bfail(OBG_EALIGN, "stream %d: frames and pitches must be 16-byte aligned", s);
-        }
-        if (sd.n_train < 1 || sd.n_train > 65535 || sd.n_test < 0) {
-            destroy(b);
-            return bfail(OBG_EINVAL, "stream %d: n_train in [1, 65535] and n_test >= 0 required", s);
-        }
-        if (sd.thr_num == 0 || sd.thr_den == 0) { destroy(b); return bfail(OBG_EINVAL, "stream %d: zero threshold", s); }
-        if (!sd.train_rgb || !sd.occ || !sd.leafset || (sd.n_test > 0 && (!sd.test_rgb || !sd.mask))) {
-            destroy(b);
-            return bfail(OBG_EINVAL, "stream %d: NULL buffer", s);
+        const obg_plan_stream &ps = streams[s];
+        const obg_geom &g = ps.geom;
+        int rc = OBG_OK;
+        if (g.width < 1 || g.height < 1 || g.depth < 1 || g.depth > 6)
+            rc = bfail(OBG_EINVAL, "stream %d: width, height >= 1 and depth in [1, 6] required", s);
+        else if (g.region_w || g.region_h)
+            rc = bfail(OBG_EINVAL, "stream %d: regions are not batched", s);
+        else if (g.row_pitch < 3LL * g.width || g.frame_pitch < (int64_t)g.height * g.row_pitch ||
+                 g.frame_pitch > 0x7FFFFFFFLL)
+            rc = bfail(OBG_EINVAL, "stream %d: bad pitches", s);
+        else if (g.row_pitch % 16 || g.frame_pitch % 16)
+            rc = bfail(OBG_EALIGN, "stream %d: pitches must be multiples of 16 bytes", s);
+        else if (ps.max_train < 0 || ps.max_train > 65535 || ps.max_test < 0)
+            rc = bfail(OBG_EINVAL, "stream %d: max_train in [0, 65535] and max_test >= 0 required", s);
+        else if (ps.thr_num == 0 || ps.thr_den == 0)
+            rc = bfail(OBG_EINVAL, "stream %d: zero threshold", s);
+        else if ((int64_t)g.height * 4 * ((g.width + 63) / 64) > (1LL << 30))
+            rc = bfail(OBG_EINVAL, "stream %d: frame too large", s);
+        if (rc != OBG_OK) {
+            destroy(p);
+            return rc;
         }
         BatchStreamDev h{};
         StripArgs &a = h.a;
@@ -593,91 +756,104 @@ int obg_batch_create(const obg_stream_desc *streams, int32_t n_streams, uint32_t
         a.div_tile = make_fastdiv((uint32_t)a.gpr);
         a.occ_test = tune(OBG_TUNE_OCC_BLIND, g.depth <= 5 ? 2 : 1) == 2;
         a.mask_row_words = (g.width + 63) / 64;
-        if ((int64_t)g.height * a.gpr > (1LL << 30)) { destroy(b); return bfail(OBG_EINVAL, "stream %d: frame too large", s); }
-        h.groups = g.height * a.gpr;
-        h.train_rgb = sd.train_rgb;
-        h.test_rgb = sd.test_rgb;
-        h.occ = sd.occ;
-        h.leaf = sd.leafset;
-        h.mask = sd.mask;
+        h.stream = s;
         h.depth = g.depth;
-        h.n_train = sd.n_train;
-        h.n_test = sd.n_test;
+        h.groups = g.height * a.gpr;
         h.words = leaf_words(g.depth);
         h.valid_bits = leaf_count(g.depth) < 32 ? leaf_count(g.depth) : 32;
-        const uint64_t need = (uint64_t)sd.thr_num * (uint64_t)sd.n_train;
-        const uint64_t kmin = (need + sd.thr_den - 1) / sd.thr_den;
-        h.empty = kmin > (uint64_t)sd.n_train ? 1 : 0;
-        h.kmin = h.empty ? 0u : (uint32_t)kmin;
-        h.planes = 0;
-        while ((1 << h.planes) <= sd.n_train) ++h.planes;
-        b->max_words = std::max(b->max_words, h.words);
-        b->px_train += (int64_t)g.width * g.height * sd.n_train;
-        b->px_test += (int64_t)g.width * g.height * sd.n_test;
-        b->h.push_back(h);
+        h.thr_num = ps.thr_num;
+        h.thr_den = ps.thr_den;
+        h.max_train = ps.max_train;
+        h.max_test = ps.max_test;
+        p->max_words = std::max(p->max_words, h.words);
+        p->h.push_back(h);
     }
-    // descriptors sorted by depth (outputs are addressed through them, so the
+    // slots sorted by depth (outputs are addressed through them, so the
     // order is free): each depth's streams are one contiguous group
-    std::stable_sort(b->h.begin(), b->h.end(),
+    std::stable_sort(p->h.begin(), p->h.end(),
                      [](const BatchStreamDev &x, const BatchStreamDev &y) { return x.depth < y.depth; });
+    p->slot_of.assign(n_streams, 0);
     for (int s = 0; s < n_streams; ++s) {
-        if (b->groups.empty() || b->groups.back().depth != b->h[s].depth)
-            b->groups.push_back(DepthGroup{b->h[s].depth, s, s, 0, 0});
-        b->groups.back().s1 = s + 1;
+        if (p->groups.empty() || p->groups.back().depth != p->h[s].depth)
+            p->groups.push_back(DepthGroup{p->h[s].depth, s, s, 0, 0});
+        p->groups.back().s1 = s + 1;
+        p->h[s].group = (int32_t)p->groups.size() - 1;
+        p->slot_of[p->h[s].stream] = s;
     }
-    // every descriptor is valid: only now touch the device
-    if (hipGetDevice(&b->device) != hipSuccess) { destroy(b); return bfail(OBG_EHIP, "no device"); }
+    // every description is valid: only now touch the device
+    if (hipGetDevice(&p->device) != hipSuccess) {
+        destroy(p);
+        return bfail(OBG_EHIP, "no device");
+    }
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
-        b->cus = cus;
-    hipError_t e = hipMalloc(&b->d, sizeof(BatchStreamDev) * n_streams);
-    if (e == hipSuccess) e = hipMalloc(&b->d_sum, sizeof(unsigned long long));
-    if (e != hipSuccess) { destroy(b); return bfail(OBG_ENOMEM, "descriptor allocation: %s", hipGetErrorString(e)); }
-    b->shape = Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 1) == 2 ? 1 : 0};
-    int rc = plan_items(b);
-    if (rc == OBG_OK && (flags & OBG_BATCH_AUTOTUNE)) rc = autotune(b, stream);
-    if (rc == OBG_OK && !(flags & OBG_BATCH_NO_GRAPH)) {
-        if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+        p->cus = cus;
+    hipError_t e = hipMalloc(&p->d, sizeof(BatchStreamDev) * n_streams);
+    if (e == hipSuccess) e = hipMalloc(&p->d_slot_of, sizeof(int32_t) * n_streams);
+    if (e == hipSuccess) e = hipMalloc(&p->d_totals, sizeof(int64_t) * kTotals);
+    if (e == hipSuccess) e = hipMalloc(&p->d_sum, sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_slot_of, p->slot_of.data(), sizeof(int32_t) * n_streams, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        destroy(p);
+        return bfail(OBG_ENOMEM, "plan allocation: %s", hipGetErrorString(e));
+    }
+    p->shape = Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 1) == 2 ? 1 : 0};
+    int rc = plan_items(p);
+    if (rc == OBG_OK && tune(OBG_TUNE_BATCH_GRAPH, 1) == 1) {
+        if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
             rc = bfail(OBG_EHIP, "capture stream");
-        else if ((rc = build_graph(b)) == OBG_OK)
-            b->use_graph = true;
+        else if ((rc = build_graph(p)) == OBG_OK)
+            p->use_graph = true;
     }
     if (rc != OBG_OK) {
-        destroy(b);
+        destroy(p);
         return rc;
     }
-    *out = b;
+    *out = p;
     return OBG_OK;
 }
 
-int obg_batch_run(obg_batch *b, hipStream_t stream) {
-    if (!b) return bfail(OBG_EINVAL, "batch is NULL");
-    return run_once(b, stream);
+int obg_plan_tune(obg_plan *p, const obg_work_item *items, int32_t n_items, hipStream_t stream) {
+    int rc = check_run_args(p, items, n_items);
+    if (rc) return rc;
+    if (n_items == 0) return OBG_OK;
+    if (hipStreamSynchronize(stream) != hipSuccess) return bfail(OBG_EHIP, "tune: stream sync");
+    rc = autotune(p, items, n_items, stream);
+    if (rc == OBG_OK && p->use_graph) rc = build_graph(p);
+    if (rc == OBG_OK && hipStreamSynchronize(stream) != hipSuccess) rc = bfail(OBG_EHIP, "tune: stream sync");
+    if (rc != OBG_OK) p->use_graph = false;
+    return rc;
 }
 
-int obg_batch_info_get(const obg_batch *b, obg_batch_info *out) {
-    if (!b || !out) return bfail(OBG_EINVAL, "NULL argument");
+int obg_batch_run(obg_plan *p, const obg_work_item *items, int32_t n_items, hipStream_t stream) {
+    int rc = check_run_args(p, items, n_items);
+    if (rc) return rc;
+    if (n_items == 0) return OBG_OK;
+    return run_once(p, items, n_items, stream, p->use_graph);
+}
+
+int obg_plan_info_get(const obg_plan *p, obg_plan_info *out) {
+    if (!p || !out) return bfail(OBG_EINVAL, "NULL argument");
     std::memset(out, 0, sizeof(*out));
-    out->n_streams = b->n_streams;
-    out->train_items = b->train_items;
-    out->classify_items = b->classify_items;
-    out->pixels_train = b->px_train;
-    out->pixels_test = b->px_test;
-    out->train_block = b->shape.train_block;
-    out->train_wg_per_cu = b->shape.train_wpc;
-    out->train_items_per_wg = b->shape.train_items_per_wg;
-    out->classify_block = b->shape.classify_block;
-    out->classify_wg_per_cu = b->shape.classify_wpc;
-    out->classify_span = b->shape.classify_span;
-    out->classify_round_robin = b->shape.classify_rr;
-    out->per_depth_launches = b->shape.per_depth;
-    out->graph = b->use_graph ? 1 : 0;
-    out->tune_candidates = b->tune_candidates;
-    out->tune_default_ms = b->tune_default_ms;
-    out->tune_best_ms = b->tune_best_ms;
+    out->n_streams = p->n_streams;
+    out->max_train_items = p->max_train_items;
+    out->max_classify_items = p->max_classify_items;
+    out->train_block = p->shape.train_block;
+    out->train_wg_per_cu = p->shape.train_wpc;
+    out->train_items_per_wg = p->shape.train_items_per_wg;
+    out->classify_block = p->shape.classify_block;
+    out->classify_wg_per_cu = p->shape.classify_wpc;
+    out->classify_span = p->shape.classify_span;
+    out->classify_round_robin = p->shape.classify_rr;
+    out->per_depth_launches = p->shape.per_depth;
+    out->graph = p->use_graph ? 1 : 0;
+    out->tune_candidates = p->tune_candidates;
+    out->tune_default_ms = p->tune_default_ms;
+    out->tune_best_ms = p->tune_best_ms;
     return OBG_OK;
 }
 
-void obg_batch_destroy(obg_batch *b) { destroy(b); }
+void obg_plan_destroy(obg_plan *p) { destroy(p); }
 
 }  // extern "C"

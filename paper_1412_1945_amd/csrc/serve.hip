@@ -247,7 +247,9 @@ struct StateHeader {
     int32_t n_streams, window;
 };
 struct StateStream {
-    int32_t width, height, depth, n_train, region_w, region_h, ring_len, pad;
+    // order: 0 = bitsets in key order, 1 = region bitsets in the compact LDS
+    // order (the stream's passes all run with compact tables)
+    int32_t width, height, depth, n_train, region_w, region_h, ring_len, order;
     int64_t next_frame;
     uint64_t tree_bytes;
 };
@@ -266,8 +268,9 @@ SchedStream sched_stream(const obg_serve_stream &c) {
     return SchedStream{c.width, c.height, c.depth, c.n_train, nreg};
 }
 
-StateStream state_record(const obg_serve_stream &c, int window, int64_t next_frame) {
+StateStream state_record(const obg_serve_stream &c, int window, int64_t next_frame, bool native = false) {
     StateStream r{};
+    r.order = native ? 1 : 0;
     r.width = c.width;
     r.height = c.height;
     r.depth = c.depth;
@@ -369,7 +372,10 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         for (int s = 0; s < ns; ++s) {
             StateStream r;
             std::memcpy(&r, p + sizeof(StateHeader) + (uint64_t)s * sizeof(StateStream), sizeof r);
-            StateStream want = state_record(cfg->streams[s], cfg->remerge_window, r.next_frame);
+            StateStream want = state_record(cfg->streams[s], cfg->remerge_window, r.next_frame, D[s].native);
+            if (r.order != want.order)
+                return sfail(OBG_EINVAL, "state_in: the stream's bitsets were stored in another bit order (a "
+                                         "different OBG_TUNE_LAYOUT setting); restore under the setting that wrote it");
             if (std::memcmp(&r, &want, sizeof r) != 0 || r.next_frame < 0 ||
                 r.next_frame + cfg->n_arrivals[s] > (int64_t)0x7FFFFFFF)
                 return sfail(OBG_EINVAL, "state_in: stream record does not match the stream");
@@ -713,7 +719,8 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         std::memcpy(p, &h, sizeof h);
         uint8_t *data = p + sizeof(StateHeader) + (uint64_t)ns * sizeof(StateStream);
         for (int s = 0; s < ns && rc == OBG_OK; ++s) {
-            const StateStream r = state_record(cfg->streams[s], cfg->remerge_window, first[s] + cfg->n_arrivals[s]);
+            const StateStream r =
+                state_record(cfg->streams[s], cfg->remerge_window, first[s] + cfg->n_arrivals[s], D[s].native);
             std::memcpy(p + sizeof(StateHeader) + (uint64_t)s * sizeof(StateStream), &r, sizeof r);
             const uint64_t ring_b = (uint64_t)r.ring_len * r.tree_bytes;
             std::memset(data, 0, pad8(r.tree_bytes) + pad8(ring_b));

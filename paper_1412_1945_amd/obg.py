@@ -35,29 +35,35 @@ class Geom(ctypes.Structure):
     ]
 
 
-class StreamDesc(ctypes.Structure):
+class PlanStream(ctypes.Structure):
+    _fields_ = [("geom", Geom), ("thr_num", ctypes.c_uint32), ("thr_den", ctypes.c_uint32),
+                ("max_train", ctypes.c_int32), ("max_test", ctypes.c_int32)]
+
+
+class WorkItem(ctypes.Structure):
     _fields_ = [
-        ("geom", Geom),
-        ("train_rgb", ctypes.c_void_p), ("n_train", ctypes.c_int32),
-        ("thr_num", ctypes.c_uint32), ("thr_den", ctypes.c_uint32),
-        ("test_rgb", ctypes.c_void_p), ("n_test", ctypes.c_int32),
+        ("stream", ctypes.c_int32), ("n_train", ctypes.c_int32), ("n_test", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("train_rgb", ctypes.c_void_p), ("test_rgb", ctypes.c_void_p),
         ("occ", ctypes.c_void_p), ("leafset", ctypes.c_void_p), ("mask", ctypes.c_void_p),
     ]
 
 
-class BatchInfo(ctypes.Structure):
+class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("n_streams", ctypes.c_int32),
-        ("train_items", ctypes.c_int64), ("classify_items", ctypes.c_int64),
-        ("pixels_train", ctypes.c_int64), ("pixels_test", ctypes.c_int64),
+        ("max_train_items", ctypes.c_int64), ("max_classify_items", ctypes.c_int64),
         ("train_block", ctypes.c_int32), ("train_wg_per_cu", ctypes.c_int32),
         ("train_items_per_wg", ctypes.c_int32),
         ("classify_block", ctypes.c_int32), ("classify_wg_per_cu", ctypes.c_int32),
         ("classify_span", ctypes.c_int32),
+        ("classify_round_robin", ctypes.c_int32), ("per_depth_launches", ctypes.c_int32),
         ("graph", ctypes.c_int32), ("tune_candidates", ctypes.c_int32),
         ("tune_default_ms", ctypes.c_double), ("tune_best_ms", ctypes.c_double),
-        ("classify_round_robin", ctypes.c_int32), ("per_depth_launches", ctypes.c_int32),
     ]
+
+
+ITEM_OK, ITEM_BAD_STREAM, ITEM_BAD_COUNT, ITEM_NULL, ITEM_ALIGN, ITEM_DUPLICATE = 0, 1, 2, 3, 4, 5
 
 
 class ServeStream(ctypes.Structure):
@@ -120,11 +126,11 @@ def load() -> ctypes.CDLL:
             "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
             "obg_probe": (ctypes.c_int, [ctypes.c_int, P, P, I64, P, I32, P]),
-            "obg_batch_create": (ctypes.c_int, [ctypes.POINTER(StreamDesc), I32, U32, P,
-                                                ctypes.POINTER(ctypes.c_void_p)]),
-            "obg_batch_run": (ctypes.c_int, [P, P]),
-            "obg_batch_info_get": (ctypes.c_int, [P, ctypes.POINTER(BatchInfo)]),
-            "obg_batch_destroy": (None, [P]),
+            "obg_plan_create": (ctypes.c_int, [ctypes.POINTER(PlanStream), I32, ctypes.POINTER(ctypes.c_void_p)]),
+            "obg_plan_tune": (ctypes.c_int, [P, P, I32, P]),
+            "obg_batch_run": (ctypes.c_int, [P, P, I32, P]),
+            "obg_plan_info_get": (ctypes.c_int, [P, ctypes.POINTER(PlanInfo)]),
+            "obg_plan_destroy": (None, [P]),
             "obg_serve_run": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(ServeStats)]),
             "obg_serve_state_bytes": (I64, [ctypes.POINTER(ServeStream), I32, I32]),
             "obg_last_error": (ctypes.c_char_p, []),
@@ -141,7 +147,7 @@ def load() -> ctypes.CDLL:
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
             "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_score", "obg_tune_set", "obg_tune_get", "obg_probe",
-            "obg_batch_create", "obg_batch_run", "obg_batch_info_get", "obg_batch_destroy",
+            "obg_plan_create", "obg_plan_tune", "obg_batch_run", "obg_plan_info_get", "obg_plan_destroy",
             "obg_serve_run", "obg_serve_state_bytes", "obg_last_error", "obg_version"]
 
 
@@ -278,7 +284,7 @@ def obg_score(g: FrameGeom, mask: torch.Tensor, truth: torch.Tensor, n_frames: i
 
 TUNE_KEYS = {"train_block": 0, "occ_blind": 1, "occ_wg_per_cu": 2,
              "classify_wg_per_cu": 3, "classify_span": 4, "classify_block": 5, "layout": 6, "interleave": 7, "mask_stage": 8,
-             "region_chunks": 9, "batch_per_depth": 10}
+             "region_chunks": 9, "batch_per_depth": 10, "batch_graph": 11}
 
 
 def obg_tune_set(key, value: int):
@@ -309,28 +315,31 @@ def obg_probe(kind: int, src: torch.Tensor, dst: Optional[torch.Tensor], nbytes:
         raise ObgError(rc, "probe arguments rejected")
 
 
-BATCH_AUTOTUNE, BATCH_NO_GRAPH = 1, 2
+class Plan:
+    """Owner of an obg_plan handle."""
 
-
-class Batch:
-    """Owner of an obg_batch handle plus references to its buffers (the library
-    keeps their device pointers, so they must outlive the batch)."""
-
-    def __init__(self, handle, keep):
+    def __init__(self, handle, n_streams):
         self.h = handle
-        self._keep = keep
+        self.n_streams = n_streams
 
-    def run(self, stream=None):
-        _check(load().obg_batch_run(self.h, _stream(stream)))
+    def run(self, items: torch.Tensor, n_items: Optional[int] = None, stream=None):
+        """obg_batch_run on a device array of work items (see work_items)."""
+        n = _n_items(items, n_items)
+        _check(load().obg_batch_run(self.h, _ptr(items), n, _stream(stream)))
+
+    def tune(self, items: torch.Tensor, n_items: Optional[int] = None, stream=None):
+        """obg_plan_tune: time the launch shapes on this work and keep the fastest."""
+        n = _n_items(items, n_items)
+        _check(load().obg_plan_tune(self.h, _ptr(items), n, _stream(stream)))
 
     def info(self) -> dict:
-        bi = BatchInfo()
-        _check(load().obg_batch_info_get(self.h, ctypes.byref(bi)))
-        return {name: getattr(bi, name) for name, _ in BatchInfo._fields_}
+        pi = PlanInfo()
+        _check(load().obg_plan_info_get(self.h, ctypes.byref(pi)))
+        return {name: getattr(pi, name) for name, _ in PlanInfo._fields_}
 
     def close(self):
         if self.h:
-            load().obg_batch_destroy(self.h)
+            load().obg_plan_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -340,29 +349,60 @@ class Batch:
             pass
 
 
-def obg_batch_create(streams, flags: int = 0, stream=None) -> Batch:
-    """streams: list of dicts with keys geom (FrameGeom), train (uint8 tensor),
-    n_train, thr (num, den), test (uint8 tensor or None), n_test, occ, leafset,
-    mask (tensors as for the one-stream calls)."""
-    arr = (StreamDesc * len(streams))()
-    keep = []
+def _n_items(items: torch.Tensor, n_items: Optional[int]) -> int:
+    _need(items, torch.uint8, 0, "items")
+    have = items.numel() // ctypes.sizeof(WorkItem)
+    n = have if n_items is None else n_items
+    if n > have:
+        raise ValueError(f"items hold {have} work items, {n} requested")
+    return n
+
+
+def obg_plan_create(streams) -> Plan:
+    """streams: list of dicts with keys geom (FrameGeom), thr (num, den),
+    max_train, max_test."""
+    arr = (PlanStream * len(streams))()
     for i, sd in enumerate(streams):
-        g = sd["geom"]
-        _frames_ok(g, sd["train"], sd["n_train"])
-        _need(sd["occ"], torch.int32, sd["n_train"] * g.words, "occ")
-        _need(sd["leafset"], torch.int32, g.words, "leafset")
-        if sd["n_test"] > 0:
-            _frames_ok(g, sd["test"], sd["n_test"])
-            _need(sd["mask"], torch.int64, sd["n_test"] * g.height * g.mask_row_words, "mask")
         num, den = sd["thr"]
-        arr[i] = StreamDesc(g.c(), sd["train"].data_ptr(), sd["n_train"], num, den,
-                            sd["test"].data_ptr() if sd["n_test"] > 0 else None, sd["n_test"],
-                            sd["occ"].data_ptr(), sd["leafset"].data_ptr(),
-                            sd["mask"].data_ptr() if sd["n_test"] > 0 else None)
-        keep.append(sd)
+        arr[i] = PlanStream(sd["geom"].c(), num, den, sd["max_train"], sd["max_test"])
     h = ctypes.c_void_p()
-    _check(load().obg_batch_create(arr, len(streams), flags, _stream(stream), ctypes.byref(h)))
-    return Batch(h, keep)
+    _check(load().obg_plan_create(arr, len(streams), ctypes.byref(h)))
+    return Plan(h, len(streams))
+
+
+def work_items(entries, device="cuda") -> torch.Tensor:
+    """Pack work items into a device array (uint8 tensor of obg_work_item).
+    entries: list of dicts with keys stream, geom (FrameGeom), n_train, n_test
+    and the tensors train, test, occ, leafset, mask (None where a count is 0;
+    leafset is read when n_train is 0 and n_test > 0).  Sizes are checked
+    here; the run checks the rest and writes each item's status."""
+    arr = (WorkItem * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        g, T, N = e["geom"], e.get("n_train", 0), e.get("n_test", 0)
+        if T > 0:
+            _frames_ok(g, e["train"], T)
+            _need(e["occ"], torch.int32, T * g.words, "occ")
+        if T > 0 or N > 0:
+            _need(e["leafset"], torch.int32, g.words, "leafset")
+        if N > 0:
+            _frames_ok(g, e["test"], N)
+            _need(e["mask"], torch.int64, N * g.height * g.mask_row_words, "mask")
+        arr[i] = WorkItem(e["stream"], T, N, -1,
+                          e["train"].data_ptr() if T > 0 else None, e["test"].data_ptr() if N > 0 else None,
+                          e["occ"].data_ptr() if T > 0 else None,
+                          e["leafset"].data_ptr() if (T > 0 or N > 0) else None,
+                          e["mask"].data_ptr() if N > 0 else None)
+    raw = bytes(memoryview(arr).cast("B"))[: len(entries) * ctypes.sizeof(WorkItem)]
+    return torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device) if raw else \
+        torch.zeros(0, dtype=torch.uint8, device=device)
+
+
+def item_status(items: torch.Tensor) -> list:
+    """Status of every work item of a finished run (OBG_ITEM_*)."""
+    host = items.cpu().numpy().tobytes()
+    n = len(host) // ctypes.sizeof(WorkItem)
+    arr = (WorkItem * max(1, n)).from_buffer_copy(host + bytes(ctypes.sizeof(WorkItem) * (1 - min(1, n))))
+    return [arr[i].status for i in range(n)]
 
 
 def _serve_streams(streams):

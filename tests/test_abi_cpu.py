@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol(lib):
     L = ctypes.CDLL(lib.LIB_PATH)
     for name in declared_functions():
         assert hasattr(L, name), name
-    assert set(declared_functions()) <= set(lib.exported_symbols()) | {"obg_batch_create", "obg_batch_run", "obg_batch_destroy", "obg_batch_info", "obg_serve_run"}
+    assert set(declared_functions()) == set(lib.exported_symbols())
 
 
 def test_sizes(lib):
@@ -65,6 +65,8 @@ def _geom(lib, **kw):
 
 
 FAKE = ctypes.c_void_p(0x100000)   # never dereferenced: every case fails validation first
+# the serving loop's ingest callback: int (*)(void *ctx, const obg_ingest_item *, int32_t, hipStream_t)
+INGEST_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p)
 
 
 @pytest.mark.parametrize("kw,code", [
@@ -155,22 +157,57 @@ def test_binding_refuses_cpu_tensors(lib):
                             torch.zeros(16, dtype=torch.int32))
 
 
-def test_batch_rejects_bad_streams(lib):
+def test_plan_rejects_bad_streams(lib):
     import ctypes as C
     L = _raw(lib)
     g = _geom(lib)
-    good = dict(geom=g, train_rgb=FAKE.value, n_train=4, thr_num=1, thr_den=2, test_rgb=FAKE.value,
-                n_test=2, occ=FAKE.value, leafset=FAKE.value, mask=FAKE.value)
+    good = dict(geom=g, thr_num=1, thr_den=2, max_train=4, max_test=2)
     out = C.c_void_p()
-    for bad, code in [(dict(n_train=0), -1), (dict(thr_num=0), -1), (dict(occ=None), -1),
+    for bad, code in [(dict(max_train=-1), -1), (dict(max_train=70000), -1), (dict(max_test=-1), -1),
+                      (dict(thr_num=0), -1), (dict(thr_den=0), -1),
                       (dict(geom=_geom(lib, depth=7)), -1), (dict(geom=_geom(lib, region_w=16, region_h=16)), -1),
-                      (dict(train_rgb=0x100008), -2)]:
+                      (dict(geom=_geom(lib, row_pitch=200, frame_pitch=1600)), -2)]:
         d = dict(good)
         d.update(bad)
-        arr = (lib.StreamDesc * 1)(lib.StreamDesc(**d))
-        assert L.obg_batch_create(arr, 1, 0, None, C.byref(out)) == code, (bad, L.obg_last_error())
+        arr = (lib.PlanStream * 1)(lib.PlanStream(**d))
+        assert L.obg_plan_create(arr, 1, C.byref(out)) == code, (bad, L.obg_last_error())
         assert not out.value
-    assert L.obg_batch_create(None, 0, 0, None, C.byref(out)) == -1
+    assert L.obg_plan_create(None, 0, C.byref(out)) == -1
+    arr = (lib.PlanStream * 1)(lib.PlanStream(**good))
+    assert L.obg_plan_create(arr, 0, C.byref(out)) == -1
+    assert L.obg_plan_create(arr, 8193, C.byref(out)) == -1
+    assert L.obg_plan_create(arr, 1, None) == -1
+    # a run on no plan, or with more items than the plan has streams
+    assert L.obg_batch_run(None, FAKE, 1, None) == -1
+    assert L.obg_plan_tune(None, FAKE, 1, None) == -1
+    L.obg_plan_destroy(None)
+
+
+def test_abi_struct_layouts(lib, tmp_path):
+    """Sizes and field offsets of the C structs of include/obg.h, as a C
+    compiler lays them out, equal those of the ctypes binding."""
+    import ctypes as C
+    structs = {"obg_geom": lib.Geom, "obg_plan_stream": lib.PlanStream, "obg_work_item": lib.WorkItem,
+               "obg_plan_info": lib.PlanInfo, "obg_serve_stream": lib.ServeStream,
+               "obg_serve_config": lib.ServeConfig, "obg_serve_stats": lib.ServeStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "obg.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c11", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True, capture_output=True)
+    got = dict(line.split() for line in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                       check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[cname]) == C.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[f"{cname}.{f}"]) == getattr(py, f).offset, f"{cname}.{f}"
 
 
 def test_serve_checkpoint_size_and_refusal(lib):
@@ -188,14 +225,23 @@ def test_serve_checkpoint_size_and_refusal(lib):
     assert lib.obg_serve_state_bytes(streams, 0) == -1
     arrivals = [np.array([0.0, 0.1, 0.2]), np.array([0.0, 0.1])]
     bad = np.zeros(want, dtype=np.uint8)
+    calls = []
+
+    @INGEST_FN
+    def ingest(ctx, items, n, stream):
+        calls.append(n)
+        return 0
+
+    cb = ctypes.cast(ingest, ctypes.c_void_p).value
     with pytest.raises(lib.ObgError) as e:
-        # the ingest callback is never reached: the state is checked first
-        lib.obg_serve_run(streams, arrivals, 1, 0, remerge_period=10, remerge_window=10, state_in=bad)
+        # the state is checked before any device work
+        lib.obg_serve_run(streams, arrivals, cb, 0, remerge_period=10, remerge_window=10, state_in=bad)
     assert e.value.code == -1
     with pytest.raises(lib.ObgError) as e:
-        lib.obg_serve_run(streams, [np.array([0.0, float("nan"), 0.2]), arrivals[1]], 1, 0,
+        lib.obg_serve_run(streams, [np.array([0.0, float("nan"), 0.2]), arrivals[1]], cb, 0,
                           remerge_period=10, remerge_window=10)
     assert e.value.code == -1 and "finite" in str(e.value)
+    assert calls == []
 
 
 def test_tune_keys_match_header_and_refuse_bad_values(lib):

@@ -1,5 +1,5 @@
-"""Batched form: many streams in one persistent launch per step, against the
-one-stream calls (bit for bit) and against the oracle."""
+"""Batched form: a plan over many streams, run on device work items, against
+the one-stream calls (bit for bit) and against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -45,33 +45,65 @@ def _mixed(obg, seed):
     return out
 
 
-def _one_stream_reference(obg, s):
+def _plan(obg, streams, max_train=None, max_test=None):
+    return obg.obg_plan_create([{"geom": s["geom"], "thr": s["thr"],
+                                 "max_train": s["n_train"] if max_train is None else max_train,
+                                 "max_test": s["n_test"] if max_test is None else max_test} for s in streams])
+
+
+def _items(obg, streams, which=None):
+    which = range(len(streams)) if which is None else which
+    return obg.work_items([dict(s, stream=i) for i, s in ((i, streams[i]) for i in which)])
+
+
+def _one_stream_reference(obg, s, leaf_in=None):
+    """One launch per frame, as a plain caller would."""
     g, T, N = s["geom"], s["n_train"], s["n_test"]
-    occ = obg.empty_occ(g, T)
-    leaf = obg.empty_leafset(g)
-    for f in range(T):                     # one launch per frame, as a plain caller would
+    occ = obg.empty_occ(g, T) if T else None
+    leaf = obg.empty_leafset(g) if leaf_in is None else leaf_in
+    for f in range(T):
         obg.obg_train_frame(g, s["train"][f], 1, occ[f])
-    obg.obg_merge(g, occ, T, 0, T, s["thr"][0], s["thr"][1], leaf)
+    if T:
+        obg.obg_merge(g, occ, T, 0, T, s["thr"][0], s["thr"][1], leaf)
     mask = obg.empty_mask(g, N) if N else None
     for f in range(N):
         obg.obg_classify(g, s["test"][f], 1, leaf, mask[f])
     return occ, leaf, mask
 
 
-@pytest.mark.parametrize("flags,per_depth", [(0, 1), (2, 1), (1, 1), (0, 2), (2, 2)],
-                         ids=["graph", "no_graph", "autotune", "per_depth_graph", "per_depth_no_graph"])
-def test_batch_equals_one_stream_calls_and_oracle(env, flags, per_depth):
+def _oracle_check(O, s, leaf_in=None):
+    g = s["geom"]
+    if leaf_in is None:
+        f = O.Forest(g.width, g.height, g.depth)
+        model = f.merge(f.add_frames(s["host"][: s["n_train"]]), *s["thr"])
+        assert np.array_equal(s["leafset"].cpu().numpy().view(np.uint32).reshape(1, -1), model.leafset())
+    else:
+        model = O.Model.from_leafset(leaf_in, g.width, g.height, g.depth)
+    for t in range(s["n_test"]):
+        want = model.classify(s["host"][s["n_train"] + t])
+        assert np.array_equal(s["mask"][t].cpu().numpy().view(np.uint64), want), f"frame {t}"
+
+
+@pytest.mark.parametrize("tune,per_depth,graph", [(False, 1, 1), (False, 1, 2), (True, 1, 1), (False, 2, 1),
+                                                   (False, 2, 2)],
+                         ids=["graph", "no_graph", "tuned", "per_depth_graph", "per_depth_no_graph"])
+def test_plan_equals_one_stream_calls_and_oracle(env, tune, per_depth, graph):
     obg, O = env
-    streams = _mixed(obg, 11 + flags + 10 * (per_depth - 1))
-    print(f"[case] batch flags={flags} per_depth={per_depth} streams={len(streams)}", flush=True)
+    streams = _mixed(obg, 11 + (1 if tune else 0) + 10 * (per_depth - 1) + 3 * (graph - 1))
+    print(f"[case] plan tune={tune} per_depth={per_depth} graph={graph} streams={len(streams)}", flush=True)
     obg.obg_tune_set("batch_per_depth", per_depth)
+    obg.obg_tune_set("batch_graph", graph)
     try:
-        batch = obg.obg_batch_create(streams, flags=flags)
+        plan = _plan(obg, streams)
     finally:
         obg.obg_tune_set("batch_per_depth", 0)
-    info = batch.info()
-    assert info["graph"] == (0 if flags & 2 else 1)
-    if not flags & 1:
+        obg.obg_tune_set("batch_graph", 0)
+    items = _items(obg, streams)
+    if tune:
+        plan.tune(items)
+    info = plan.info()
+    assert info["graph"] == (1 if graph == 1 else 0)
+    if not tune:
         assert info["per_depth_launches"] == per_depth - 1
     for rep in range(2):                   # outputs are rewritten completely on every run
         for s in streams:
@@ -79,8 +111,9 @@ def test_batch_equals_one_stream_calls_and_oracle(env, flags, per_depth):
             s["leafset"].fill_(-1)
             if s["mask"] is not None:
                 s["mask"].fill_(-1)
-        batch.run()
+        plan.run(items)
         torch.cuda.synchronize()
+        assert obg.item_status(items) == [obg.ITEM_OK] * len(streams)
         for i, s in enumerate(streams):
             occ, leaf, mask = _one_stream_reference(obg, s)
             torch.cuda.synchronize()
@@ -89,15 +122,117 @@ def test_batch_equals_one_stream_calls_and_oracle(env, flags, per_depth):
             if mask is not None:
                 assert torch.equal(s["mask"], mask), f"stream {i} masks"
     for i, s in enumerate(streams):
-        g = s["geom"]
-        f = O.Forest(g.width, g.height, g.depth)
-        idx = f.add_frames(s["host"][: s["n_train"]])
-        model = f.merge(idx, *s["thr"])
-        assert np.array_equal(s["leafset"].cpu().numpy().view(np.uint32).reshape(1, -1), model.leafset())
-        for t in range(s["n_test"]):
-            want = model.classify(s["host"][s["n_train"] + t])
-            assert np.array_equal(s["mask"][t].cpu().numpy().view(np.uint64), want), f"stream {i} frame {t}"
-    batch.close()
+        _oracle_check(O, s)
+    plan.close()
+
+
+def test_plan_serves_changing_work(env):
+    """One plan (and its one captured graph) runs two different item arrays:
+    other frames and buffers, fewer frames than the plan's maxima, a subset of
+    the streams, and streams that only classify against a given leaf set.
+    Each run equals the one-stream calls and the oracle; streams no item
+    names keep their buffers."""
+    obg, O = env
+    rng = np.random.default_rng(101)
+    shapes = [(64, 8, 3, 6, 3), (130, 9, 6, 5, 2), (96, 31, 5, 7, 3), (333, 7, 4, 4, 2), (48, 48, 2, 5, 3)]
+    thr = [(1, 2), (3, 10), (7, 10), (1, 1), (1, 2)]
+    first = [_stream(obg, rng, W, H, d, T, N, thr[i], ncol=int(rng.integers(3, 30)))
+             for i, (W, H, d, T, N) in enumerate(shapes)]
+    plan = _plan(obg, first, max_train=8, max_test=4)
+    info0 = plan.info()
+    print("[case] plan run 1: all streams", flush=True)
+    items1 = _items(obg, first)
+    plan.run(items1)
+    torch.cuda.synchronize()
+    assert obg.item_status(items1) == [0] * len(first)
+    for i, s in enumerate(first):
+        occ, leaf, mask = _one_stream_reference(obg, s)
+        torch.cuda.synchronize()
+        assert torch.equal(s["occ"], occ) and torch.equal(s["leafset"], leaf) and torch.equal(s["mask"], mask), i
+        _oracle_check(O, s)
+    # run 2: new frames and buffers; stream 1 classifies only (against the
+    # leaf set of another stream of its depth), stream 3 is not named, stream
+    # 4 trains only, counts below and at the maxima
+    second = {}
+    for i, (W, H, d, T, N) in enumerate(shapes):
+        T2 = [8, 0, 2, None, 3][i]
+        N2 = [4, 3, 1, None, 0][i]
+        if T2 is None:
+            continue
+        s = _stream(obg, rng, W, H, d, max(T2, 1), N2, thr[i], ncol=int(rng.integers(3, 30)))
+        s["n_train"] = T2
+        if T2 == 0:
+            s["train"], s["occ"] = None, None
+            s["host"] = [None] + s["host"][1:]
+        second[i] = s
+    foreign = first[1]["leafset"].clone()
+    second[1]["leafset"].copy_(foreign)
+    sentinel = {k: first[3][k].clone() for k in ("occ", "leafset", "mask")}
+    print("[case] plan run 2: a subset, classify-only and train-only items", flush=True)
+    items2 = obg.work_items([dict(s, stream=i) for i, s in second.items()])
+    plan.run(items2)
+    torch.cuda.synchronize()
+    assert obg.item_status(items2) == [0] * len(second)
+    assert plan.info() == info0
+    for i, s in second.items():
+        if s["n_train"] == 0:
+            s["host"] = s["host"][1:]
+            leaf_in = foreign.clone()
+            _, _, mask = _one_stream_reference(obg, s, leaf_in=leaf_in)
+            torch.cuda.synchronize()
+            assert torch.equal(s["leafset"], foreign), "a classify-only item's leaf set is input"
+            assert torch.equal(s["mask"], mask)
+            _oracle_check(O, s, leaf_in=foreign.cpu().numpy().view(np.uint32).reshape(1, -1))
+            continue
+        occ, leaf, mask = _one_stream_reference(obg, s)
+        torch.cuda.synchronize()
+        assert torch.equal(s["occ"], occ) and torch.equal(s["leafset"], leaf), i
+        if s["n_test"]:
+            assert torch.equal(s["mask"], mask), i
+        _oracle_check(O, s)
+    for k, v in sentinel.items():
+        assert torch.equal(first[3][k], v), f"stream 3 not named in run 2, but its {k} changed"
+    plan.close()
+
+
+def test_plan_item_status(env):
+    """Items the run cannot take are skipped with their reason; nothing of
+    them is written, and the valid items of the same run are exact."""
+    obg, O = env
+    rng = np.random.default_rng(202)
+    streams = [_stream(obg, rng, 64, 8, 4, 3, 2, (1, 2), ncol=9), _stream(obg, rng, 80, 6, 5, 4, 2, (1, 2), ncol=9)]
+    plan = _plan(obg, streams)
+    good = [dict(streams[0], stream=0)]
+    bad_mask = obg.empty_mask(streams[1]["geom"], 2).fill_(7)
+    bad = [dict(streams[1], stream=5),                          # no such stream
+           dict(streams[1], stream=1, n_train=5),                # above max_train
+           dict(streams[1], stream=1, mask=bad_mask),            # fine: taken
+           dict(streams[1], stream=1, mask=bad_mask)]            # the stream again
+    items = obg.work_items(good + bad)
+    plan.run(items)
+    torch.cuda.synchronize()
+    assert obg.item_status(items) == [0, obg.ITEM_BAD_STREAM, obg.ITEM_BAD_COUNT, 0, obg.ITEM_DUPLICATE]
+    for s in streams:
+        if s is streams[1]:
+            s = dict(s, mask=bad_mask)
+        occ, leaf, mask = _one_stream_reference(obg, s)
+        torch.cuda.synchronize()
+        assert torch.equal(s["occ"], occ) and torch.equal(s["leafset"], leaf) and torch.equal(s["mask"], mask)
+    # NULL and misaligned buffers: fields patched in the packed items
+    import ctypes
+    W = ctypes.sizeof(obg.WorkItem)
+    items = obg.work_items([dict(streams[0], stream=0), dict(streams[1], stream=1)])
+    host = items.cpu().numpy().copy()
+    host[W + obg.WorkItem.mask.offset: W + obg.WorkItem.mask.offset + 8] = 0
+    host[obg.WorkItem.train_rgb.offset] += 8
+    items = torch.from_numpy(host).cuda()
+    streams[1]["mask"].fill_(3)
+    before = streams[1]["mask"].clone()
+    plan.run(items)
+    torch.cuda.synchronize()
+    assert obg.item_status(items) == [obg.ITEM_ALIGN, obg.ITEM_NULL]
+    assert torch.equal(streams[1]["mask"], before)
+    plan.close()
 
 
 def test_batch_mixed_resolutions(env):
@@ -115,8 +250,9 @@ def test_batch_mixed_resolutions(env):
                         "n_test": 3, "occ": obg.empty_occ(g, T), "leafset": obg.empty_leafset(g),
                         "mask": obg.empty_mask(g, 3), "spec": spec, "frames": fr})
     print(f"[case] mixed batch of {len(streams)} streams", flush=True)
-    batch = obg.obg_batch_create(streams)
-    batch.run()
+    plan = _plan(obg, streams)
+    items = _items(obg, streams)
+    plan.run(items)
     torch.cuda.synchronize()
     for i, s in enumerate(streams):
         occ, leaf, mask = _one_stream_reference(obg, s)
@@ -132,4 +268,4 @@ def test_batch_mixed_resolutions(env):
         assert np.array_equal(s["leafset"].cpu().numpy().view(np.uint32).reshape(1, -1), model.leafset())
         want = model.classify(host[s["n_train"] + 2])
         assert np.array_equal(s["mask"][2].cpu().numpy().view(np.uint64), want)
-    batch.close()
+    plan.close()

@@ -2,7 +2,10 @@
 
 The oracle checks every training occupancy and the merged leaf set in full,
 a few whole test frames, and pixels sampled uniformly over every test frame
-(Check Color of each sampled pixel, one by one).
+(Check Color of each sampled pixel, one by one).  Every workload's masks are
+also checked against a model that leaves both classes in them, and such
+checks assert that the masks compared hold between 0.1 % and 99.9 %
+foreground.
 """
 import numpy as np
 import pytest
@@ -29,7 +32,58 @@ def _generate(spec, device="cuda"):
     return frames
 
 
-def _run_and_check(env, wl, whole_frames, n_samples, seed):
+FG_MIN, FG_MAX = 0.001, 0.999   # a discriminating mask holds both classes
+
+
+def _sample_pixels(frames, T, N, width, height, n_samples, seed):
+    """n_samples (frame, y, x) positions uniformly over the test frames and
+    their RGB bytes (gathered on the GPU)."""
+    rng = np.random.default_rng(seed)
+    fs = rng.integers(0, N, n_samples)
+    ys = rng.integers(0, height, n_samples)
+    xs = rng.integers(0, width, n_samples)
+    px = frames[T + torch.from_numpy(fs).cuda(), torch.from_numpy(ys).cuda()]
+    cols = torch.from_numpy(xs).cuda() * 3
+    rgb = torch.stack([px.gather(1, (cols + c).view(-1, 1)).view(-1) for c in range(3)], dim=1).cpu().numpy()
+    return fs, ys, xs, rgb
+
+
+def _check_masks(model, frames, T, N, mask, whole_frames, n_samples, seed, label, mixed=True):
+    """Whole test frames against Check Color of every pixel (the oracle's
+    classify), and sampled pixels of every test frame one by one.  With
+    `mixed`, the compared masks must hold both classes.  Returns the number
+    of foreground bits compared."""
+    width, height = model.width, model.height
+    g_mask = mask.cpu().numpy().view(np.uint64)
+    fg_bits, px_whole = 0, 0
+    for t in whole_frames:
+        want = model.classify(frames[T + t].cpu().numpy())
+        assert np.array_equal(g_mask[t], want), f"{label}: mask of test frame {t}"
+        fg_bits += int(np.unpackbits(want.view(np.uint8)).sum())
+        px_whole += width * height
+    fs, ys, xs, rgb = _sample_pixels(frames, T, N, width, height, n_samples, seed)
+    fg_samples = 0
+    for k in range(n_samples):
+        f, y, x = int(fs[k]), int(ys[k]), int(xs[k])
+        fg = not model.check_pixel(x, y, int(rgb[k, 0]), int(rgb[k, 1]), int(rgb[k, 2]))
+        bit = (int(g_mask[f, y, x >> 6]) >> (x & 63)) & 1
+        assert bit == int(fg), f"{label}: pixel ({x},{y}) of test frame {f}"
+        fg_samples += int(fg)
+    print(f"[case] {label}: foreground {fg_bits / px_whole:.4f} of the whole frames, "
+          f"{fg_samples}/{n_samples} samples", flush=True)
+    if mixed:
+        assert FG_MIN < fg_bits / px_whole < FG_MAX, f"{label}: whole frames hold one class only"
+        assert FG_MIN < fg_samples / n_samples < FG_MAX, f"{label}: samples hold one class only"
+    return fg_bits + fg_samples
+
+
+def _run_and_check(env, wl, whole_frames, n_samples, seed, own_mixed):
+    """Trees, merge and masks of a full-size workload in the bench's launch
+    configuration (all test frames in one obg_classify call).  The masks are
+    checked twice: against the stream's own merged tree (own_mixed: whether
+    those masks hold both classes on this recipe), and against the merged
+    tree of another seed's small stream, whose masks always do."""
+    from oracle import models
     obg, O = env
     spec = wl.streams[0]
     d = wl.depth[0]
@@ -56,36 +110,31 @@ def _run_and_check(env, wl, whole_frames, n_samples, seed):
         assert np.array_equal(g_occ[i], forest.export(i)), f"occupancy of training frame {i}"
     model = forest.merge(idx, num, den)
     assert np.array_equal(leaf.cpu().numpy().view(np.uint32), model.leafset()), "merged leaf set"
-    g_mask = mask.cpu().numpy().view(np.uint64)
-    for t in whole_frames:
-        want = model.classify(frames[T + t].cpu().numpy())
-        assert np.array_equal(g_mask[t], want), f"mask of test frame {t}"
-    rng = np.random.default_rng(seed)
-    fs = rng.integers(0, N, n_samples)
-    ys = rng.integers(0, spec.height, n_samples)
-    xs = rng.integers(0, spec.width, n_samples)
-    px = frames[T + torch.from_numpy(fs).cuda(), torch.from_numpy(ys).cuda()]
-    cols = torch.from_numpy(xs).cuda() * 3
-    rgb = torch.stack([px.gather(1, (cols + c).view(-1, 1)).view(-1) for c in range(3)], dim=1).cpu().numpy()
-    for k in range(n_samples):
-        f, y, x = int(fs[k]), int(ys[k]), int(xs[k])
-        fg = not model.check_pixel(x, y, int(rgb[k, 0]), int(rgb[k, 1]), int(rgb[k, 2]))
-        bit = (int(g_mask[f, y, x >> 6]) >> (x & 63)) & 1
-        assert bit == int(fg), f"pixel ({x},{y}) of test frame {f}"
+    _check_masks(model, frames, T, N, mask, whole_frames, n_samples, seed, f"{wl.name} own model", mixed=own_mixed)
+    print(f"[case] {wl.name}: classify against another stream's merged tree", flush=True)
+    other = models.foreign_model(spec.width, spec.height, d, rw, rh)
+    leaf_f = torch.from_numpy(models.foreign_leafset(d, g.n_regions).view(np.int32)).cuda()
+    mask.fill_(-1)
+    obg.obg_classify(g, frames[T:], N, leaf_f, mask)
+    torch.cuda.synchronize()
+    fg = _check_masks(other, frames, T, N, mask, whole_frames, n_samples, seed + 100, f"{wl.name} foreign model")
+    assert fg > 0
     del frames
     torch.cuda.empty_cache()
 
 
 def test_plain_1080p_full(env):
-    """1920x1080, depth 5, 50 training + 1000 test frames, threshold 1/2."""
+    """1920x1080, depth 5, 50 training + 1000 test frames, threshold 1/2.  The
+    stream's own merged tree holds every depth-5 cell on this recipe, so its
+    masks are all background; the foreign model's masks hold both classes."""
     from synth.frames import cfg1
-    _run_and_check(env, cfg1(), whole_frames=[0, 1, 333, 999], n_samples=20000, seed=1)
+    _run_and_check(env, cfg1(), whole_frames=[0, 1, 333, 999], n_samples=20000, seed=1, own_mixed=False)
 
 
 def test_region_4k_full(env):
     """3840x2160 in 32x32 regions, depth 4, 30 training + 500 test frames."""
     from synth.frames import cfg2
-    _run_and_check(env, cfg2(), whole_frames=[0, 499], n_samples=20000, seed=2)
+    _run_and_check(env, cfg2(), whole_frames=[0, 499], n_samples=20000, seed=2, own_mixed=True)
 
 
 def test_largest_frame(env):
@@ -125,4 +174,4 @@ def test_largest_frame(env):
     got = mask.cpu().numpy().view(np.uint64)[0]
     assert np.array_equal(got, want), "mask of the test frame"
     ones = int(np.unpackbits(want.view(np.uint8)).sum())
-    assert 0 < ones < W * H
+    assert FG_MIN < ones / (W * H) < FG_MAX

@@ -204,6 +204,41 @@ def test_serve_checkpoint_resume(env):
     assert e.value.code == -1
 
 
+def test_serve_checkpoint_records_bit_order(env):
+    """A region stream whose passes pick wide LDS tables keeps its bitsets in
+    key order; with OBG_TUNE_LAYOUT = 2 (compact tables) the same stream keeps
+    them in the compact order.  The checkpoint records the order, so a state
+    written under one setting and restored under the other is refused, and a
+    state restored under the setting that wrote it resumes exactly."""
+    obg, O = env
+    from synth.frames import StreamSpec
+    from synth.fast import poisson_arrivals
+    specs = [StreamSpec(64, 32, 5, 60, seed=23, stream=0, fg="ellipses", fg_coverage=0.15, bimodal_frac=0.2)]
+    streams = [{"width": 64, "height": 32, "depth": 3, "n_train": 5, "thr": (1, 2), "region_w": 32, "region_h": 32}]
+    arrivals = poisson_arrivals([300.0], 0.2, seed=9)
+    n = [len(arrivals[0])]
+    cut = n[0] // 2
+    size = obg.obg_serve_state_bytes(streams, WINDOW)
+    for write_layout, read_layout in [(0, 2), (2, 0)]:
+        print(f"[case] serve checkpoint order: written under layout {write_layout}, read under {read_layout}",
+              flush=True)
+        mid = np.zeros(size, dtype=np.uint8)
+        obg.obg_tune_set("layout", write_layout)
+        try:
+            _, ref, _ = _serve(obg, specs, streams, arrivals, [0], speed=1000.0, n_frames=n)
+            _, s1, _ = _serve(obg, specs, streams, [arrivals[0][:cut]], [0], speed=1000.0, n_frames=n,
+                              state_out=mid)
+            _, s2, _ = _serve(obg, specs, streams, [arrivals[0][cut:]], [0], speed=1000.0, n_frames=n,
+                              state_in=mid)
+            assert np.array_equal(s2[0, cut:n[0]], ref[0, cut:n[0]])
+            obg.obg_tune_set("layout", read_layout)
+            with pytest.raises(obg.ObgError) as e:
+                _serve(obg, specs, streams, [arrivals[0][cut:]], [0], speed=1000.0, n_frames=n, state_in=mid)
+            assert e.value.code == -1 and "bit order" in str(e.value)
+        finally:
+            obg.obg_tune_set("layout", 0)
+
+
 def test_serve_out_of_order_arrivals(env):
     """Arrival times that go back within a stream (late frames) still serve
     each stream in frame order: the masks equal those of the in-order run."""

@@ -156,6 +156,47 @@ def check_redraw(O, seed, mutant=0):
             assert np.array_equal(out, fr[:, : 3 * W])
 
 
+def check_pixel_checks(O, seed, mutant=0):
+    """Check Color of one pixel at a time (the checker of the sampled pixels of
+    full-size runs) against brute-force membership of the pixel's quantised
+    colour in its region's kept set.  Regions are not square, frames are not
+    square, and the leaf sets are sparse (the intersection of the training
+    frames' trees), so a mixed-up channel or region index changes answers.
+    Every answer also equals the frame-wide labels of the same model."""
+    rng = np.random.default_rng(seed)
+    for trial, (rw, rh) in enumerate([(3, 2), (5, 1), (2, 4), (0, 0), (4, 3)]):
+        d = int(rng.integers(1, 9)) if trial else 3
+        s = 8 - d
+        W, H = int(rng.integers(7, 14)), int(rng.integers(3, 7))
+        T = int(rng.integers(2, 5))
+        frames = brute.tiny_frames(rng, T + 2, W, H, n_colours=int(rng.integers(3, 9)), row_pitch=3 * W + 5)
+        train, test = frames[:T], frames[T:]
+        f = O.Forest(W, H, d, rw, rh, mutant=mutant)
+        model = f.merge(f.add_frames(train), T, T)
+        kept = brute.merged_sets(train, W, H, d, T, T, rw, rh)
+        reg = brute.region_ids(W, H, rw, rh)
+        for fr in test + train:
+            px = np.asarray(fr[:, : 3 * W], dtype=np.int64).reshape(H, W, 3)
+            labels, _ = brute.unpack_mask(model.classify(fr), W)
+            for y in range(H):
+                for x in range(W):
+                    r, g, b = (int(v) for v in px[y, x])
+                    bg = model.check_pixel(x, y, r, g, b)
+                    assert bg == ((r >> s, g >> s, b >> s) in kept[reg[y, x]]), (trial, x, y)
+                    assert bg == (not labels[y, x]), (trial, x, y)
+        # a colour kept in one region only: background there, foreground elsewhere
+        for r0 in range(len(kept)):
+            only = kept[r0] - set().union(set(), *[kept[q] for q in range(len(kept)) if q != r0])
+            for t in sorted(only)[:2]:
+                c = [v << s for v in t]
+                for y in range(H):
+                    for x in range(W):
+                        assert model.check_pixel(x, y, *c) == (reg[y, x] == r0), (trial, t, x, y)
+        for x, y in [(-1, 0), (0, -1), (W, 0), (0, H)]:
+            with pytest.raises(IndexError):
+                model.check_pixel(x, y, 0, 0, 0)
+
+
 def check_union_and_training_background(O, seed, mutant=0):
     """Threshold of one frame: every training pixel is background."""
     rng = np.random.default_rng(seed)
@@ -198,6 +239,11 @@ def test_brute_force_groups(oracle_lib, seed):
 @pytest.mark.parametrize("seed", range(2))
 def test_redraw_keeps_top_bits(oracle_lib, seed):
     check_redraw(oracle_lib, 500 + seed)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_check_pixel_against_brute_force(oracle_lib, seed):
+    check_pixel_checks(oracle_lib, 6000 + seed)
 
 
 def test_brute_force_direct_depth(oracle_lib):
@@ -375,6 +421,8 @@ MUTANTS = {
     8: "mask polarity inverted",
     9: "numberOfTrees off by one in the merge test",
     10: "a group's tree built from its first frame only",
+    11: "one pixel's check takes red and blue exchanged",
+    12: "one pixel's check looks its region up in the transposed grid",
 }
 
 
@@ -387,6 +435,7 @@ def _pin_battery(O, mutant):
     check_union_and_training_background(O, 3000, mutant)
     check_groups(O, 4000, mutant)
     check_redraw(O, 5000, mutant)
+    check_pixel_checks(O, 6000, mutant)
 
 
 @pytest.mark.parametrize("mutant", sorted(MUTANTS))
