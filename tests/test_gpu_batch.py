@@ -201,17 +201,29 @@ def test_plan_item_status(env):
     obg, O = env
     rng = np.random.default_rng(202)
     streams = [_stream(obg, rng, 64, 8, 4, 3, 2, (1, 2), ncol=9), _stream(obg, rng, 80, 6, 5, 4, 2, (1, 2), ncol=9)]
-    plan = _plan(obg, streams)
+    # three more plan streams that no item names (a run holds at most as many
+    # items as the plan has streams): their buffers must stay as they are
+    idle = [_stream(obg, rng, 32, 4, 3, 2, 1, (1, 2), ncol=5) for _ in range(3)]
+    for s in idle:
+        s["occ"].fill_(5), s["leafset"].fill_(5), s["mask"].fill_(5)
+    plan = _plan(obg, streams + idle)
     good = [dict(streams[0], stream=0)]
     bad_mask = obg.empty_mask(streams[1]["geom"], 2).fill_(7)
+    # buffers that hold five training frames, so that only the plan's maximum refuses them
+    g1 = streams[1]["geom"]
+    five = torch.zeros((5, g1.height, g1.row_pitch), dtype=torch.uint8, device="cuda")
+    five_occ = obg.empty_occ(g1, 5).fill_(9)
     bad = [dict(streams[1], stream=5),                          # no such stream
-           dict(streams[1], stream=1, n_train=5),                # above max_train
+           dict(streams[1], stream=1, n_train=5, train=five, occ=five_occ),   # above max_train
            dict(streams[1], stream=1, mask=bad_mask),            # fine: taken
            dict(streams[1], stream=1, mask=bad_mask)]            # the stream again
     items = obg.work_items(good + bad)
     plan.run(items)
     torch.cuda.synchronize()
     assert obg.item_status(items) == [0, obg.ITEM_BAD_STREAM, obg.ITEM_BAD_COUNT, 0, obg.ITEM_DUPLICATE]
+    assert bool((five_occ == 9).all()), "a skipped item wrote its trees"
+    for s in idle:
+        assert bool((s["occ"] == 5).all()) and bool((s["leafset"] == 5).all()) and bool((s["mask"] == 5).all())
     for s in streams:
         if s is streams[1]:
             s = dict(s, mask=bad_mask)
