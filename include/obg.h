@@ -266,6 +266,31 @@ int obg_plan_info_get(const obg_plan *plan, obg_plan_info *out);
 void obg_plan_destroy(obg_plan *plan);
 
 /*
+ * Batched run without allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The same work and outputs as obg_plan_create(streams,
+ * n_streams) followed by obg_batch_run(plan, work_items_dev, n_items,
+ * stream), with the plan's starting launch shape and no graph, but no plan:
+ * the per-stream descriptors and the launches' item counts live in a static
+ * device array of the library (room for OBG_NOALLOC_MAX_STREAMS streams, each
+ * GPU holding its own copy until the process ends).  No device memory is
+ * allocated or freed; the descriptors are copied from host memory with
+ * hipMemcpyAsync on `stream`.
+ *   streams          host array, as for obg_plan_create (read during the call)
+ *   n_streams        1..OBG_NOALLOC_MAX_STREAMS (EINVAL otherwise)
+ *   work_items_dev   as for obg_batch_run (n_items in [0, n_streams]; each
+ *                    item's status is written)
+ * Every call on one GPU uses that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (on different HIP streams, or from
+ * several threads) race; issue them on one stream or order them.
+ * Errors as obg_plan_create and obg_batch_run; nothing is enqueued when
+ * validation fails.
+ */
+#define OBG_NOALLOC_MAX_STREAMS 256
+int obg_batch_run_noalloc(const obg_plan_stream *streams, int32_t n_streams, const obg_work_item *work_items_dev,
+                          int32_t n_items, hipStream_t stream);
+
+/*
  * Serving: continuous batching of frames that arrive from many cameras.
  *
  * obg_serve_run drives one run to completion.  Frame f of stream s arrives

@@ -27,6 +27,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -379,7 +380,21 @@ __global__ __launch_bounds__(256) void batch_checksum_kernel(const BatchStreamDe
     atomicAdd(out, h);
 }
 
+// Device memory of the no-allocation run: the slots, the plan-stream -> slot
+// map and the launch item counts of at most kNoAllocStreams streams.  Every
+// GPU the library runs on holds its own copy until the process ends.
+constexpr int kNoAllocStreams = OBG_NOALLOC_MAX_STREAMS;
+struct NoAllocLayout {
+    BatchStreamDev slots[kNoAllocStreams];
+    int32_t slot_of[kNoAllocStreams];
+    int64_t totals[kTotals];
+};
+
 }  // namespace obg
+
+// The no-allocation run's buffer (host code uses its address from
+// hipGetSymbolAddress, never this name).
+static __device__ __align__(256) uint64_t scratch[(sizeof(obg::NoAllocLayout) + 7) / 8];
 
 using namespace obg;
 
@@ -433,9 +448,9 @@ struct obg_plan {
 
 namespace {
 
-// Split every stream's frames into work items for the current shape and
-// upload the slots (their per-run fields are the prepare kernel's).
-int plan_items(obg_plan *p) {
+// Split every stream's frames into work items for the current shape (host
+// copies of the slots only).
+void split_items(obg_plan *p) {
     int64_t tgroups = 0;
     for (const auto &h : p->h) tgroups += (int64_t)h.groups * h.max_train;
     const int64_t train_wgs = (int64_t)p->cus * p->shape.train_wpc;
@@ -461,6 +476,12 @@ int plan_items(obg_plan *p) {
         p->max_train_items += gr.max_train_items;
         p->max_classify_items += gr.max_classify_items;
     }
+}
+
+// Split the work for the current shape and upload the slots (their per-run
+// fields are the prepare kernel's).
+int plan_items(obg_plan *p) {
+    split_items(p);
     hipError_t e = hipMemcpy(p->d, p->h.data(), sizeof(BatchStreamDev) * p->h.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return bfail(OBG_EHIP, "descriptor upload: %s", hipGetErrorString(e));
     return OBG_OK;
@@ -707,40 +728,30 @@ int check_run_args(const obg_plan *p, const obg_work_item *items, int32_t n_item
     return OBG_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-int obg_plan_create(const obg_plan_stream *streams, int32_t n_streams, obg_plan **out) {
-    if (!out) return bfail(OBG_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!streams || n_streams < 1) return bfail(OBG_EINVAL, "need at least one stream");
-    if (n_streams > kPlanMaxStreams) return bfail(OBG_EINVAL, "at most %d streams per plan", kPlanMaxStreams);
-    obg_plan *p = new obg_plan();
+// Validate the stream descriptions and build the plan's host slots (sorted
+// by depth), the plan-stream -> slot map and the depth groups.  Host only.
+int describe(const obg_plan_stream *streams, int32_t n_streams, obg_plan *p) {
     p->n_streams = n_streams;
+    p->h.clear();
+    p->slot_of.clear();
+    p->groups.clear();
+    p->max_words = 0;
     for (int s = 0; s < n_streams; ++s) {
         const obg_plan_stream &ps = streams[s];
         const obg_geom &g = ps.geom;
-        int rc = OBG_OK;
         if (g.width < 1 || g.height < 1 || g.depth < 1 || g.depth > 6)
-            rc = bfail(OBG_EINVAL, "stream %d: width, height >= 1 and depth in [1, 6] required", s);
-        else if (g.region_w || g.region_h)
-            rc = bfail(OBG_EINVAL, "stream %d: regions are not batched", s);
-        else if (g.row_pitch < 3LL * g.width || g.frame_pitch < (int64_t)g.height * g.row_pitch ||
-                 g.frame_pitch > 0x7FFFFFFFLL)
-            rc = bfail(OBG_EINVAL, "stream %d: bad pitches", s);
-        else if (g.row_pitch % 16 || g.frame_pitch % 16)
-            rc = bfail(OBG_EALIGN, "stream %d: pitches must be multiples of 16 bytes", s);
-        else if (ps.max_train < 0 || ps.max_train > 65535 || ps.max_test < 0)
-            rc = bfail(OBG_EINVAL, "stream %d: max_train in [0, 65535] and max_test >= 0 required", s);
-        else if (ps.thr_num == 0 || ps.thr_den == 0)
-            rc = bfail(OBG_EINVAL, "stream %d: zero threshold", s);
-        else if ((int64_t)g.height * 4 * ((g.width + 63) / 64) > (1LL << 30))
-            rc = bfail(OBG_EINVAL, "stream %d: frame too large", s);
-        if (rc != OBG_OK) {
-            destroy(p);
-            return rc;
-        }
+            return bfail(OBG_EINVAL, "stream %d: width, height >= 1 and depth in [1, 6] required", s);
+        if (g.region_w || g.region_h) return bfail(OBG_EINVAL, "stream %d: regions are not batched", s);
+        if (g.row_pitch < 3LL * g.width || g.frame_pitch < (int64_t)g.height * g.row_pitch ||
+            g.frame_pitch > 0x7FFFFFFFLL)
+            return bfail(OBG_EINVAL, "stream %d: bad pitches", s);
+        if (g.row_pitch % 16 || g.frame_pitch % 16)
+            return bfail(OBG_EALIGN, "stream %d: pitches must be multiples of 16 bytes", s);
+        if (ps.max_train < 0 || ps.max_train > 65535 || ps.max_test < 0)
+            return bfail(OBG_EINVAL, "stream %d: max_train in [0, 65535] and max_test >= 0 required", s);
+        if (ps.thr_num == 0 || ps.thr_den == 0) return bfail(OBG_EINVAL, "stream %d: zero threshold", s);
+        if ((int64_t)g.height * 4 * ((g.width + 63) / 64) > (1LL << 30))
+            return bfail(OBG_EINVAL, "stream %d: frame too large", s);
         BatchStreamDev h{};
         StripArgs &a = h.a;
         a.width = g.width;
@@ -780,6 +791,47 @@ int obg_plan_create(const obg_plan_stream *streams, int32_t n_streams, obg_plan 
         p->h[s].group = (int32_t)p->groups.size() - 1;
         p->slot_of[p->h[s].stream] = s;
     }
+    return OBG_OK;
+}
+
+// The launch shape a plan starts from.
+Shape default_shape() { return Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 1) == 2 ? 1 : 0}; }
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+int scratch_address(int dev, NoAllocLayout **out) {
+    if (dev < 0 || dev >= kMaxDevices) return bfail(OBG_EHIP, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return bfail(OBG_EHIP, "address of the no-allocation buffer: %s", hipGetErrorString(e));
+        g_scratch[dev] = ptr;
+    }
+    *out = static_cast<NoAllocLayout *>(g_scratch[dev]);
+    return OBG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int obg_plan_create(const obg_plan_stream *streams, int32_t n_streams, obg_plan **out) {
+    if (!out) return bfail(OBG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!streams || n_streams < 1) return bfail(OBG_EINVAL, "need at least one stream");
+    if (n_streams > kPlanMaxStreams) return bfail(OBG_EINVAL, "at most %d streams per plan", kPlanMaxStreams);
+    obg_plan *p = new obg_plan();
+    int rc = describe(streams, n_streams, p);
+    if (rc != OBG_OK) {
+        destroy(p);
+        return rc;
+    }
     // every description is valid: only now touch the device
     if (hipGetDevice(&p->device) != hipSuccess) {
         destroy(p);
@@ -798,8 +850,8 @@ int obg_plan_create(const obg_plan_stream *streams, int32_t n_streams, obg_plan 
         destroy(p);
         return bfail(OBG_ENOMEM, "plan allocation: %s", hipGetErrorString(e));
     }
-    p->shape = Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 1) == 2 ? 1 : 0};
-    int rc = plan_items(p);
+    p->shape = default_shape();
+    rc = plan_items(p);
     if (rc == OBG_OK && tune(OBG_TUNE_BATCH_GRAPH, 1) == 1) {
         if (hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking) != hipSuccess)
             rc = bfail(OBG_EHIP, "capture stream");
@@ -831,6 +883,43 @@ int obg_batch_run(obg_plan *p, const obg_work_item *items, int32_t n_items, hipS
     if (rc) return rc;
     if (n_items == 0) return OBG_OK;
     return run_once(p, items, n_items, stream, p->use_graph);
+}
+
+int obg_batch_run_noalloc(const obg_plan_stream *streams, int32_t n_streams, const obg_work_item *items,
+                          int32_t n_items, hipStream_t stream) {
+    if (!streams || n_streams < 1) return bfail(OBG_EINVAL, "need at least one stream");
+    if (n_streams > kNoAllocStreams)
+        return bfail(OBG_EINVAL, "at most %d streams without allocation (got %d)", kNoAllocStreams, n_streams);
+    // host copies of the slots: one per thread, reused from call to call
+    thread_local obg_plan p;
+    int rc = describe(streams, n_streams, &p);
+    if (rc == OBG_OK) rc = check_run_args(&p, items, n_items);
+    if (rc != OBG_OK || n_items == 0) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return bfail(OBG_EHIP, "no device");
+    NoAllocLayout *buf = nullptr;
+    if ((rc = scratch_address(dev, &buf)) != OBG_OK) return rc;
+    int cus = 0;
+    p.cus = (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+                ? cus
+                : 256;
+    p.device = dev;
+    p.shape = default_shape();
+    split_items(&p);
+    p.d = buf->slots;
+    p.d_slot_of = buf->slot_of;
+    p.d_totals = buf->totals;
+    // the fixed fields of the slots and the slot map; the prepare kernel
+    // writes every per-run field and item count, so nothing is cleared first
+    hipError_t e = hipMemcpyAsync(p.d, p.h.data(), sizeof(BatchStreamDev) * n_streams, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p.d_slot_of, p.slot_of.data(), sizeof(int32_t) * n_streams, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) rc = run_once(&p, items, n_items, stream, false);
+    else rc = bfail(OBG_EHIP, "descriptor upload: %s", hipGetErrorString(e));
+    p.d = nullptr;
+    p.d_slot_of = nullptr;
+    p.d_totals = nullptr;
+    return rc;
 }
 
 int obg_plan_info_get(const obg_plan *p, obg_plan_info *out) {

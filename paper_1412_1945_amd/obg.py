@@ -131,6 +131,7 @@ def load() -> ctypes.CDLL:
             "obg_batch_run": (ctypes.c_int, [P, P, I32, P]),
             "obg_plan_info_get": (ctypes.c_int, [P, ctypes.POINTER(PlanInfo)]),
             "obg_plan_destroy": (None, [P]),
+            "obg_batch_run_noalloc": (ctypes.c_int, [ctypes.POINTER(PlanStream), I32, P, I32, P]),
             "obg_serve_run": (ctypes.c_int, [ctypes.POINTER(ServeConfig), ctypes.POINTER(ServeStats)]),
             "obg_serve_state_bytes": (I64, [ctypes.POINTER(ServeStream), I32, I32]),
             "obg_last_error": (ctypes.c_char_p, []),
@@ -148,6 +149,7 @@ def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
             "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_score", "obg_tune_set", "obg_tune_get", "obg_probe",
             "obg_plan_create", "obg_plan_tune", "obg_batch_run", "obg_plan_info_get", "obg_plan_destroy",
+            "obg_batch_run_noalloc",
             "obg_serve_run", "obg_serve_state_bytes", "obg_last_error", "obg_version"]
 
 
@@ -358,16 +360,31 @@ def _n_items(items: torch.Tensor, n_items: Optional[int]) -> int:
     return n
 
 
-def obg_plan_create(streams) -> Plan:
-    """streams: list of dicts with keys geom (FrameGeom), thr (num, den),
-    max_train, max_test."""
-    arr = (PlanStream * len(streams))()
+def _plan_streams(streams):
+    arr = (PlanStream * max(1, len(streams)))()
     for i, sd in enumerate(streams):
         num, den = sd["thr"]
         arr[i] = PlanStream(sd["geom"].c(), num, den, sd["max_train"], sd["max_test"])
+    return arr
+
+
+def obg_plan_create(streams) -> Plan:
+    """streams: list of dicts with keys geom (FrameGeom), thr (num, den),
+    max_train, max_test."""
     h = ctypes.c_void_p()
-    _check(load().obg_plan_create(arr, len(streams), ctypes.byref(h)))
+    _check(load().obg_plan_create(_plan_streams(streams), len(streams), ctypes.byref(h)))
     return Plan(h, len(streams))
+
+
+NOALLOC_MAX_STREAMS = 256
+
+
+def obg_batch_run_noalloc(streams, items: torch.Tensor, n_items: Optional[int] = None, stream=None):
+    """obg_batch_run_noalloc: the batched run of these stream descriptions
+    (as for obg_plan_create) on a device array of work items, with no device
+    memory allocated by the library."""
+    n = _n_items(items, n_items)
+    _check(load().obg_batch_run_noalloc(_plan_streams(streams), len(streams), _ptr(items), n, _stream(stream)))
 
 
 def work_items(entries, device="cuda") -> torch.Tensor:

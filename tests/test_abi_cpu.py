@@ -183,6 +183,33 @@ def test_plan_rejects_bad_streams(lib):
     L.obg_plan_destroy(None)
 
 
+def test_noalloc_run_rejects_before_touching_the_device(lib):
+    """The no-allocation batched run validates like a plan and its run, and
+    its stream limit is the header's."""
+    import ctypes as C
+    L = _raw(lib)
+    src = open(HEADER).read()
+    assert int(re.search(r"#define OBG_NOALLOC_MAX_STREAMS\s+(\d+)", src).group(1)) == lib.NOALLOC_MAX_STREAMS
+    good = dict(geom=_geom(lib), thr_num=1, thr_den=2, max_train=4, max_test=2)
+    for bad, code in [(dict(max_train=-1), -1), (dict(thr_num=0), -1), (dict(geom=_geom(lib, depth=7)), -1),
+                      (dict(geom=_geom(lib, region_w=16, region_h=16)), -1),
+                      (dict(geom=_geom(lib, row_pitch=200, frame_pitch=1600)), -2)]:
+        d = dict(good)
+        d.update(bad)
+        arr = (lib.PlanStream * 1)(lib.PlanStream(**d))
+        assert L.obg_batch_run_noalloc(arr, 1, FAKE, 1, None) == code, (bad, L.obg_last_error())
+    n = lib.NOALLOC_MAX_STREAMS + 1
+    arr = (lib.PlanStream * n)(*[lib.PlanStream(**good)] * n)
+    assert L.obg_batch_run_noalloc(arr, n, FAKE, 1, None) == -1
+    assert b"without allocation" in L.obg_last_error()
+    assert L.obg_batch_run_noalloc(None, 1, FAKE, 1, None) == -1
+    assert L.obg_batch_run_noalloc(arr, 0, FAKE, 1, None) == -1
+    assert L.obg_batch_run_noalloc(arr, 2, FAKE, 3, None) == -1          # more items than streams
+    assert L.obg_batch_run_noalloc(arr, 2, None, 1, None) == -1          # items NULL
+    assert L.obg_batch_run_noalloc(arr, 2, C.c_void_p(0x100004), 1, None) == -2   # misaligned items
+    assert L.obg_batch_run_noalloc(arr, 2, FAKE, 0, None) == 0           # nothing to do
+
+
 def test_abi_struct_layouts(lib, tmp_path):
     """Sizes and field offsets of the C structs of include/obg.h, as a C
     compiler lays them out, equal those of the ctypes binding."""
