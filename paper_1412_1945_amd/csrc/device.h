@@ -60,6 +60,53 @@ __host__ __device__ constexpr uint32_t key_from_lds(uint32_t l, int d, int lay) 
     return k;
 }
 
+// Whole key words <-> LDS words (d >= 2).  The 32 keys of key word kw vary in
+// key bits 0..4 = B'0, G'0, R'0, B'1, G'1.  In both LDS orders B'0 and B'1 are
+// LDS index bits 0 and 1, so for each of the 8 values q of (G'0, R'0, G'1) the
+// four keys that differ in B'0, B'1 are one aligned nibble of one LDS word.
+// That nibble sits at LDS index lds_from_key(32 kw) | nib_lds(q) (the two
+// parts have disjoint bits), and its bits (B'1 B'0 = 0..3) are the key-word
+// bits nib_key(q) + {0, 1, 8, 9}.
+template <int D, int LAY>
+__host__ __device__ constexpr uint32_t nib_lds(int q) {
+    return lds_from_key((uint32_t)(((q >> 2) << 4) | (((q >> 1) & 1) << 2) | ((q & 1) << 1)), D, LAY);
+}
+__host__ __device__ constexpr int nib_key(int q) { return 2 * (q & 1) + 4 * ((q >> 1) & 1) + 16 * (q >> 2); }
+__host__ __device__ inline uint32_t nib_spread(uint32_t n) { return (n & 3u) | ((n & 0xCu) << 6); }
+__host__ __device__ inline uint32_t nib_pick(uint32_t w, int off) {
+    return ((w >> off) & 3u) | (((w >> (off + 8)) & 3u) << 2);
+}
+
+// Key word kw of one tree's LDS table (gather of 8 nibbles).
+template <int D, int LAY>
+__host__ __device__ inline uint32_t key_word_from_table(const uint32_t *tab, uint32_t kw) {
+    static_assert(D >= 2, "a key word holds at least 32 keys from d = 2 on");
+    const uint32_t lbase = lds_from_key(kw << 5, D, LAY);
+    const uint32_t w0 = lbase >> 5, p0 = lbase & 31u;
+    uint32_t out = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t nl = nib_lds<D, LAY>(q);
+        out |= nib_spread((tab[w0 + (nl >> 5)] >> (p0 + (nl & 31u))) & 0xFu) << nib_key(q);
+    }
+    return out;
+}
+
+// Key word kw with bits `bits` into one tree's LDS table: or_into(word, mask)
+// is called for each non-empty nibble (8 at most).
+template <int D, int LAY, typename OrInto>
+__host__ __device__ inline void key_word_to_table(uint32_t bits, uint32_t kw, OrInto or_into) {
+    static_assert(D >= 2, "a key word holds at least 32 keys from d = 2 on");
+    const uint32_t lbase = lds_from_key(kw << 5, D, LAY);
+    const uint32_t w0 = lbase >> 5, p0 = lbase & 31u;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint32_t n = nib_pick(bits, nib_key(q));
+        const uint32_t nl = nib_lds<D, LAY>(q);
+        if (n) or_into(w0 + (nl >> 5), n << (p0 + (nl & 31u)));
+    }
+}
+
 // Exact unsigned division by a runtime-invariant divisor with one high
 // multiply (Granlund & Montgomery, PLDI 1994, unsigned case, N = 32).
 struct FastDiv {

@@ -11,6 +11,7 @@ namespace obg {
 
 // The bits of one key-order word kw are keys 32*kw + b; their LDS indices are
 // lds_from_key(32*kw) | lds_from_key(b) because the map permutes index bits.
+// From d = 2 on a key word moves as eight nibbles (device.h).
 // native: the bitsets in HBM are already in the compact LDS order (the
 // serving runtime's own rings and leaf sets); words are copied as they are.
 template <int D, int PAD>
@@ -35,13 +36,18 @@ __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, u
         uint32_t bits = leaf[i];
         if (LC < 32) bits &= (1u << (LC & 31)) - 1u;
         if (bits == 0) continue;
-        const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
         uint32_t *tile = lds + c * LW;
+        if constexpr (D >= 2) {
+            // eight nibbles per key word
+            key_word_to_table<D, PAD>(bits, (uint32_t)kw, [&](uint32_t w, uint32_t m) { atomicOr(&tile[w], m); });
+        } else {
+            const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            if ((bits >> b) & 1u) {
-                const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
-                atomicOr(&tile[l >> 5], 1u << (l & 31));
+            for (int b = 0; b < NB; ++b) {
+                if ((bits >> b) & 1u) {
+                    const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
+                    atomicOr(&tile[l >> 5], 1u << (l & 31));
+                }
             }
         }
     }
@@ -72,13 +78,17 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
     for (int i = tid; i < n_tiles * KW; i += nt) {
         const int c = i / KW;
         const int kw = i - c * KW;
-        const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
         const uint32_t *tile = lds + c * LW;
         uint32_t out = 0;
+        if constexpr (D >= 2) {
+            out = key_word_from_table<D, PAD>(tile, (uint32_t)kw);
+        } else {
+            const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
-            out |= ((tile[l >> 5] >> (l & 31)) & 1u) << b;
+            for (int b = 0; b < NB; ++b) {
+                const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
+                out |= ((tile[l >> 5] >> (l & 31)) & 1u) << b;
+            }
         }
         if (store)
             occ[i] = out;

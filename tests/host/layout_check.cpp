@@ -10,7 +10,45 @@ using namespace obg;
 static int fails = 0;
 #define CHECK(c) do { if (!(c)) { if (fails++ < 10) printf("FAIL %s line %d\n", #c, __LINE__); } } while (0)
 
+// Word-level conversion between key order and an LDS order (eight nibbles per
+// key word) against the bit-by-bit definition, on random tables.
+template <int D, int LAY>
+static void check_words(uint64_t seed) {
+    const uint32_t nkeys = 1u << (3 * D), kwords = nkeys / 32, lw = (uint32_t)lds_words(D, LAY);
+    uint32_t *key = (uint32_t *)calloc(kwords, 4), *tab = (uint32_t *)calloc(lw, 4),
+             *tab2 = (uint32_t *)calloc(lw, 4);
+    for (int trial = 0; trial < 3; ++trial) {
+        for (uint32_t i = 0; i < kwords; ++i) {
+            seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
+            key[i] = trial == 0 ? (uint32_t)seed : trial == 1 ? (uint32_t)seed & (uint32_t)(seed >> 32) : 0xFFFFFFFFu;
+        }
+        // definition: bit k of the key bitset is bit lds_from_key(k) of the table
+        for (uint32_t i = 0; i < lw; ++i) tab[i] = tab2[i] = 0;
+        for (uint32_t k = 0; k < nkeys; ++k)
+            if ((key[k >> 5] >> (k & 31)) & 1u) {
+                const uint32_t l = lds_from_key(k, D, LAY);
+                tab[l >> 5] |= 1u << (l & 31);
+            }
+        for (uint32_t kw = 0; kw < kwords; ++kw)
+            key_word_to_table<D, LAY>(key[kw], kw, [&](uint32_t w, uint32_t m) {
+                CHECK(w < lw);
+                if (w < lw) tab2[w] |= m;
+            });
+        for (uint32_t i = 0; i < lw; ++i) CHECK(tab[i] == tab2[i]);
+        for (uint32_t kw = 0; kw < kwords; ++kw) CHECK((key_word_from_table<D, LAY>(tab, kw) == key[kw]));
+    }
+    free(key);
+    free(tab);
+    free(tab2);
+}
+
 int main() {
+    check_words<2, LAY_WIDE>(1); check_words<3, LAY_WIDE>(2); check_words<4, LAY_WIDE>(3);
+    check_words<5, LAY_WIDE>(4);
+    check_words<2, LAY_COMPACT>(5); check_words<3, LAY_COMPACT>(6); check_words<4, LAY_COMPACT>(7);
+    check_words<5, LAY_COMPACT>(8); check_words<6, LAY_COMPACT>(9); check_words<7, LAY_COMPACT>(10);
+    check_words<8, LAY_COMPACT>(11);
+
     // divisors: groups per row (4*ceil(W/64)), region widths / 16, and more
     const uint32_t ds[] = {1, 2, 3, 4, 5, 7, 8, 12, 20, 60, 120, 240, 255, 256, 257, 1000, 4095,
                            65535, 65536, 65537, 1u << 20, (1u << 24) + 1, 0x7FFFFFFFu};
