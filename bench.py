@@ -58,6 +58,9 @@ def parse():
                    help="HBM traffic of the classify kernel measured with rocprofv3 counters")
     p.add_argument("--probe", action="store_true",
                    help="only run the streaming probes (read, read+write, 1 GiB copy) and print them")
+    p.add_argument("--probe-sweep", action="store_true",
+                   help="only sweep the shaped read and read+write probes over 1000 frames' bytes of the 1080p "
+                        "workload (grid, block, groups in flight, item size, phased writes) and print the table")
     return p.parse_args()
 
 
@@ -93,6 +96,62 @@ def run_probes(obg, torch, src, nbytes, reps=5):
         moved = n * (2 if kind == obg.PROBE_COPY else 1) + (n // 24 if kind == obg.PROBE_READ_WRITE else 0)
         out[name] = {"ms": round(ms, 4), "tb_s": round(moved / (ms * 1e-3) / 1e12, 3)}
     return out
+
+
+def probe_sweep(reps=3):
+    """The classify access pattern's ceiling: the shaped probes over the bytes
+    of 1000 1920x1080 frames (6.22 GB), every launch shape of the sweep, best
+    of `reps` timed runs each.  Rates count the bytes read plus, for
+    read+write, the 1/24 as many written."""
+    import torch
+    from paper_1412_1945_amd import obg
+    obg.load()
+    nbytes = (1000 * 1080 * 5760 // (48 * 4096)) * (48 * 4096)
+    src = torch.arange(nbytes // 4, dtype=torch.int32, device="cuda").view(torch.uint8)
+    dst = torch.empty(nbytes // 24 + 4096, dtype=torch.uint8, device="cuda")
+    sink = torch.empty(4096 * 1024 + 1, dtype=torch.int32, device="cuda")
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    rows = []
+
+    def timed(**kw):
+        best = None
+        for r in range(reps + 1):
+            a, b = ev(), ev()
+            a.record()
+            obg.obg_probe_shaped(src=src, dst=dst, nbytes=nbytes, sink=sink, **kw)
+            b.record()
+            torch.cuda.synchronize()
+            if r:
+                t = a.elapsed_time(b)
+                best = t if best is None else min(best, t)
+        return best
+
+    shapes = []
+    for kind in (obg.PROBE_READ, obg.PROBE_READ_WRITE):
+        for block in (256, 512, 1024):
+            for grid in (256, 512, 1024, 2048, 4096):
+                for inflight in (1, 2, 4):
+                    for span in (832, 4096):
+                        shapes.append(dict(kind=kind, grid=grid, block=block, inflight=inflight, span=span))
+    for block, grid in ((512, 256), (512, 512), (256, 512), (256, 1024)):
+        for span, phase in ((832, 4), (832, 8), (832, 16), (832, 24), (4096, 2), (4096, 4)):
+            shapes.append(dict(kind=obg.PROBE_READ_WRITE, grid=grid, block=block, inflight=1, span=span,
+                               phase_items=phase))
+    for sh in shapes:
+        n = sh["span"] * 48
+        used = (nbytes // n) * n
+        try:
+            ms = timed(**sh)
+        except obg.ObgError as e:
+            rows.append(dict(sh, error=str(e)))
+            continue
+        moved = used + (used // 24 if sh["kind"] == obg.PROBE_READ_WRITE else 0)
+        rows.append(dict(sh, ms=round(ms, 4), tb_s=round(moved / (ms * 1e-3) / 1e12, 3)))
+        print(f"# {rows[-1]}", file=sys.stderr, flush=True)
+    best = {k: max((r for r in rows if r.get("kind") == k and "tb_s" in r), key=lambda r: r["tb_s"])
+            for k in (obg.PROBE_READ, obg.PROBE_READ_WRITE)}
+    print(json.dumps({"probe_sweep": rows, "bytes": nbytes, "best_read": best[obg.PROBE_READ],
+                      "best_read_write": best[obg.PROBE_READ_WRITE]}), flush=True)
 
 
 def workload(name, n_test):
@@ -574,6 +633,8 @@ def main():
         return run_batched(a)
     if a.workload == "served":
         return run_served(a)
+    if a.probe_sweep:
+        return probe_sweep()
     import torch
     from paper_1412_1945_amd import obg
     from synth.frames import make_frames

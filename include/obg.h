@@ -488,6 +488,35 @@ int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 int obg_probe(int kind, const void *src, void *dst, int64_t bytes, uint32_t *sink, int32_t grid,
               hipStream_t stream);
 
+/*
+ * Shaped probe (measurement, not part of the method): the READ and
+ * READ_WRITE probes above with their launch shape given, so that the
+ * ceiling of the classify access pattern can be swept.
+ *   kind         OBG_PROBE_READ or OBG_PROBE_READ_WRITE
+ *   grid         workgroups, 1..65536
+ *   block        threads per workgroup: 256, 512 or 1024
+ *   inflight     48-byte groups each lane loads before it uses any: 1, 2, 4
+ *   span         groups per item (a multiple of 4 in 4..4096); items are
+ *                dealt round-robin over the workgroups; READ_WRITE writes
+ *                each item's 2 bytes per group as one run (1/24 of the bytes
+ *                read) after the item
+ *   phase_items  READ_WRITE only.  0: as above.  n > 0: every workgroup
+ *                reads n items (their output staged on chip, n * span * 2
+ *                bytes <= 64 KiB), then waits at a grid-wide counter until
+ *                every workgroup has read its n items, then writes them, so
+ *                that the chip's reads and writes are separated in time.  The
+ *                wait is bounded (a workgroup that waited too long goes on);
+ *                the launch is cooperative and fails with OBG_EHIP when the
+ *                grid cannot be resident at once.
+ * sink must hold grid * block + 1 uint32 (the last word is the phased
+ * probe's counter, cleared by the call); dst as for OBG_PROBE_READ_WRITE.
+ */
+typedef struct obg_probe_shape {
+    int32_t kind, grid, block, inflight, span, phase_items;
+} obg_probe_shape;
+int obg_probe_shaped(const obg_probe_shape *shape, const void *src, void *dst, int64_t bytes, uint32_t *sink,
+                     hipStream_t stream);
+
 /* Message of the calling thread's last failed call ("" if none). */
 const char *obg_last_error(void);
 

@@ -126,6 +126,7 @@ def load() -> ctypes.CDLL:
             "obg_tune_set": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
             "obg_tune_get": (ctypes.c_int, [ctypes.c_int]),
             "obg_probe": (ctypes.c_int, [ctypes.c_int, P, P, I64, P, I32, P]),
+            "obg_probe_shaped": (ctypes.c_int, [ctypes.POINTER(ProbeShape), P, P, I64, P, P]),
             "obg_plan_create": (ctypes.c_int, [ctypes.POINTER(PlanStream), I32, ctypes.POINTER(ctypes.c_void_p)]),
             "obg_plan_tune": (ctypes.c_int, [P, P, I32, P]),
             "obg_batch_run": (ctypes.c_int, [P, P, I32, P]),
@@ -147,7 +148,7 @@ def load() -> ctypes.CDLL:
 
 def exported_symbols():
     return ["obg_num_regions", "obg_occ_words", "obg_mask_words", "obg_train_frame",
-            "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_score", "obg_tune_set", "obg_tune_get", "obg_probe",
+            "obg_merge", "obg_merge_groups", "obg_classify", "obg_quantize", "obg_score", "obg_tune_set", "obg_tune_get", "obg_probe", "obg_probe_shaped",
             "obg_plan_create", "obg_plan_tune", "obg_batch_run", "obg_plan_info_get", "obg_plan_destroy",
             "obg_batch_run_noalloc",
             "obg_serve_run", "obg_serve_state_bytes", "obg_last_error", "obg_version"]
@@ -315,6 +316,23 @@ def obg_probe(kind: int, src: torch.Tensor, dst: Optional[torch.Tensor], nbytes:
     rc = load().obg_probe(kind, _ptr(src), _ptr(dst), nbytes, _ptr(sink), grid, _stream(stream))
     if rc != OBG_OK:
         raise ObgError(rc, "probe arguments rejected")
+
+
+class ProbeShape(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("grid", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("inflight", ctypes.c_int32), ("span", ctypes.c_int32), ("phase_items", ctypes.c_int32)]
+
+
+def obg_probe_shaped(kind: int, src: torch.Tensor, dst: Optional[torch.Tensor], nbytes: int,
+                     sink: torch.Tensor, grid: int, block: int, inflight: int, span: int,
+                     phase_items: int = 0, stream=None):
+    """The READ / READ_WRITE probe with its launch shape given (see obg.h)."""
+    _need(src, torch.uint8, nbytes, "src")
+    if dst is not None:
+        _need(dst, torch.uint8, nbytes // 24, "dst")
+    _need(sink, torch.int32, grid * block + 1, "sink")
+    sh = ProbeShape(kind, grid, block, inflight, span, phase_items)
+    _check(load().obg_probe_shaped(ctypes.byref(sh), _ptr(src), _ptr(dst), nbytes, _ptr(sink), _stream(stream)))
 
 
 class Plan:

@@ -210,6 +210,25 @@ def test_noalloc_run_rejects_before_touching_the_device(lib):
     assert L.obg_batch_run_noalloc(arr, 2, FAKE, 0, None) == 0           # nothing to do
 
 
+def test_shaped_probe_rejects_bad_shapes(lib):
+    """The shaped probe refuses shapes outside its documented ranges before it
+    touches the device."""
+    import ctypes as C
+    L = _raw(lib)
+    good = dict(kind=lib.PROBE_READ_WRITE, grid=512, block=512, inflight=2, span=832, phase_items=0)
+    for bad in [dict(kind=3), dict(grid=0), dict(grid=65537), dict(block=128), dict(inflight=3), dict(span=2),
+                dict(span=4098), dict(span=830), dict(phase_items=-1), dict(phase_items=40),
+                dict(kind=lib.PROBE_READ, phase_items=4)]:
+        d = dict(good)
+        d.update(bad)
+        sh = lib.ProbeShape(**d)
+        assert L.obg_probe_shaped(C.byref(sh), FAKE, FAKE, 1 << 30, FAKE, None) == -1, bad
+    sh = lib.ProbeShape(**good)
+    assert L.obg_probe_shaped(C.byref(sh), FAKE, None, 1 << 30, FAKE, None) == -1     # no dst for writes
+    assert L.obg_probe_shaped(C.byref(sh), FAKE, FAKE, 100, FAKE, None) == -1         # less than one item
+    assert L.obg_probe_shaped(None, FAKE, FAKE, 1 << 30, FAKE, None) == -1
+
+
 def test_abi_struct_layouts(lib, tmp_path):
     """Sizes and field offsets of the C structs of include/obg.h, as a C
     compiler lays them out, equal those of the ctypes binding."""
