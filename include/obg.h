@@ -453,6 +453,9 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
  *                               per depth present and phase
  *   OBG_TUNE_BATCH_GRAPH        1 = plans capture their steps in a HIP graph
  *                               (default), 2 = runs launch them directly
+ *   OBG_TUNE_FUSED_SPAN         16-pixel groups per work item of the fused
+ *                               classify + occupancy pass without regions
+ *                               (0 = the built-in rule)
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1
@@ -466,7 +469,8 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
 #define OBG_TUNE_REGION_CHUNKS       9
 #define OBG_TUNE_BATCH_PER_DEPTH     10
 #define OBG_TUNE_BATCH_GRAPH         11
-#define OBG_TUNE_COUNT               12
+#define OBG_TUNE_FUSED_SPAN          12
+#define OBG_TUNE_COUNT               13
 int obg_tune_set(int key, int value);
 int obg_tune_get(int key);   /* current value, 0 = default, -1 = bad key */
 

@@ -281,6 +281,11 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         target = (int64_t)cus * std::min(per_cu, tune(OBG_TUNE_OCC_WG_PER_CU, block == 1024 ? 2 : 4));
         spans = 1;
         store = true;
+    } else if ((mode & MODE_MASK) && g.reg_cols == 1 && tune(OBG_TUNE_FUSED_SPAN, 0) > 0) {
+        int want = tune(OBG_TUNE_OCC_WG_PER_CU, 4);
+        if (want > per_cu) want = per_cu;
+        target = (int64_t)cus * want;
+        spans = (groups_strip + tune(OBG_TUNE_FUSED_SPAN, 0) - 1) / tune(OBG_TUNE_FUSED_SPAN, 0);
     } else if (mode & MODE_OCC) {
         // each (frame, strip) segment of a workgroup costs one LDS flush:
         // few, large items

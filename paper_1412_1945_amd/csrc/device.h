@@ -77,33 +77,41 @@ __host__ __device__ inline uint32_t nib_pick(uint32_t w, int off) {
     return ((w >> off) & 3u) | (((w >> (off + 8)) & 3u) << 2);
 }
 
-// Key word kw of one tree's LDS table (gather of 8 nibbles).
-template <int D, int LAY>
+// Dual tables (the fused classify + occupancy pass): one table holds both
+// bitsets of a tree in word pairs, word 2w the merged leaf set's word w and
+// word 2w + 1 the frame's occupancy word w, so that one 8-byte LDS read gives
+// a pixel both bits.
+
+// Key word kw of one tree's LDS table (gather of 8 nibbles); DUAL: the
+// occupancy words of a dual table.
+template <int D, int LAY, bool DUAL = false>
 __host__ __device__ inline uint32_t key_word_from_table(const uint32_t *tab, uint32_t kw) {
     static_assert(D >= 2, "a key word holds at least 32 keys from d = 2 on");
     const uint32_t lbase = lds_from_key(kw << 5, D, LAY);
-    const uint32_t w0 = lbase >> 5, p0 = lbase & 31u;
     uint32_t out = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const uint32_t nl = nib_lds<D, LAY>(q);
-        out |= nib_spread((tab[w0 + (nl >> 5)] >> (p0 + (nl & 31u))) & 0xFu) << nib_key(q);
+        const uint32_t w = (lbase >> 5) + (nl >> 5);
+        const uint32_t n = (tab[DUAL ? 2 * w + 1 : w] >> ((lbase & 31u) + (nl & 31u))) & 0xFu;
+        out |= nib_spread(n) << nib_key(q);
     }
     return out;
 }
 
 // Key word kw with bits `bits` into one tree's LDS table: or_into(word, mask)
-// is called for each non-empty nibble (8 at most).
-template <int D, int LAY, typename OrInto>
+// is called for each non-empty nibble (8 at most); DUAL: into the leaf words
+// of a dual table.
+template <int D, int LAY, bool DUAL = false, typename OrInto>
 __host__ __device__ inline void key_word_to_table(uint32_t bits, uint32_t kw, OrInto or_into) {
     static_assert(D >= 2, "a key word holds at least 32 keys from d = 2 on");
     const uint32_t lbase = lds_from_key(kw << 5, D, LAY);
-    const uint32_t w0 = lbase >> 5, p0 = lbase & 31u;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const uint32_t n = nib_pick(bits, nib_key(q));
         const uint32_t nl = nib_lds<D, LAY>(q);
-        if (n) or_into(w0 + (nl >> 5), n << (p0 + (nl & 31u)));
+        const uint32_t w = (lbase >> 5) + (nl >> 5);
+        if (n) or_into(DUAL ? 2 * w : w, n << ((lbase & 31u) + (nl & 31u)));
     }
 }
 

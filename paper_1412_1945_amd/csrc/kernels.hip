@@ -43,11 +43,14 @@ strip_kernel(StripArgs a) {
     constexpr int KW = leaf_words(D);
     constexpr int LW = lds_words(D, PAD);
     constexpr int LC = leaf_count(D);
+    // the fused pass keeps one dual table per tile (leaf and occupancy words
+    // in pairs): one 8-byte LDS read per pixel gives both
+    constexpr bool DUAL = MASK && OCC && !CNT;
     // one tree per strip: fixed-size tables (their LDS addresses are known
     // when the kernel is compiled); several: tables sized at launch
     extern __shared__ uint32_t dyn_lds[];
-    __shared__ uint32_t st_leaf[(!REGION && MASK) ? LW : 1];
-    __shared__ uint32_t st_occ[(!REGION && OCC) ? LW : 1];
+    __shared__ uint32_t st_leaf[(!REGION && MASK) ? (DUAL ? 2 * LW : LW) : 1];
+    __shared__ uint32_t st_occ[(!REGION && OCC && !DUAL) ? LW : 1];
     // mask staging: one work item's 16-bit group masks (spans <= kStageGroups)
     __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
     uint16_t *stage = (MASK && a.stage_mask) ? st_mask : nullptr;
@@ -55,7 +58,7 @@ strip_kernel(StripArgs a) {
     // LDS tables of one strip: a chunk of at most chunk_cols regions
     const int max_tiles = REGION ? a.chunk_cols : 1;
     uint32_t *leaf_lds = REGION ? dyn_lds : st_leaf;
-    uint32_t *occ_lds = REGION ? dyn_lds + (MASK ? max_tiles * LW : 0) : st_occ;
+    uint32_t *occ_lds = DUAL ? leaf_lds : (REGION ? dyn_lds + (MASK ? max_tiles * LW : 0) : st_occ);
     const bool store = a.occ_store != 0;
     // bitsets kept in the compact LDS order (frame lists of the serving runtime)
     const bool native = LIST && PAD == LAY_COMPACT && a.native != 0;
@@ -99,14 +102,19 @@ strip_kernel(StripArgs a) {
         const bool new_seg = (s != cur_s) || (f != cur_f);
         if (OCC && new_seg && cur_f >= 0) {
             __syncthreads();
-            occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store,
-                                 native);
+            occ_from_lds<D, PAD, DUAL>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK,
+                                       store, native);
         }
         if (MASK && s != cur_s) {
+            // (a dual table is cleared whole here, occupancy bits included)
             __syncthreads();
-            leaf_to_lds<D, PAD>(a.leaf + reg0 * KW, leaf_lds, tiles, tid, BLOCK, native);
+            leaf_to_lds<D, PAD, DUAL>(a.leaf + reg0 * KW, leaf_lds, tiles, tid, BLOCK, native);
+        } else if (DUAL && new_seg) {
+            __syncthreads();
+            clear_dual_occ(occ_lds, tiles * 2 * LW, tid, BLOCK);
+            __syncthreads();
         }
-        if (OCC && new_seg) {
+        if (OCC && !DUAL && new_seg) {
             __syncthreads();
             for (int i = tid; i < tiles * LW; i += BLOCK) occ_lds[i] = 0;
             __syncthreads();
@@ -134,8 +142,8 @@ strip_kernel(StripArgs a) {
     }
     if (OCC && cur_f >= 0) {
         __syncthreads();
-        occ_from_lds<D, PAD>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK, store,
-                             native);
+        occ_from_lds<D, PAD, DUAL>(occ_lds, frame_occ<LIST>(a, cur_f, KW) + cur_reg0 * KW, cur_tiles, tid, BLOCK,
+                                   store, native);
     }
 }
 

@@ -80,44 +80,51 @@ __device__ __forceinline__ int frame_of(const ServeArgs &b, int64_t g) {
 }
 
 // Groups [gb, ge) of one frame: its occupancy is built in LDS and ORed into the
-// frame's ring slot; test frames also get their mask bits from the leaf table.
+// frame's ring slot; test frames also get their mask bits from the leaf set,
+// in one dual table (leaf and occupancy words in pairs), training frames use
+// an occupancy table in the same memory.
 template <int D, int LAY, int MODE>
-__device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, int gb, int ge, uint32_t *leaf_tab,
-                                                     uint32_t *occ_tab, bool load_leaf) {
+__device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, int gb, int ge, uint32_t *tab,
+                                                     bool load_leaf) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr int LW = lds_words(D, LAY);
     const int tid = threadIdx.x;
     const StripArgs a = fd.a;
-    if (MASK && load_leaf) leaf_to_lds<D, LAY>(fd.leaf, leaf_tab, 1, tid, kServeBlock);
-    __syncthreads();
-    for (int i = tid; i < LW; i += kServeBlock) occ_tab[i] = 0;
+    __syncthreads();   // the previous part's flush has read the table
+    if (MASK) {
+        if (load_leaf)
+            leaf_to_lds<D, LAY, true>(fd.leaf, tab, 1, tid, kServeBlock);
+        else
+            clear_dual_occ(tab, 2 * LW, tid, kServeBlock);
+    } else {
+        for (int i = tid; i < LW; i += kServeBlock) tab[i] = 0;
+    }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(fd.rgb, (uint32_t)a.frame_pitch);
     __amdgpu_buffer_rsrc_t ms = make_rsrc(nullptr, 0);
     if (MASK) ms = make_rsrc(fd.mask, (uint32_t)a.height * (uint32_t)a.mask_row_words * 8u);
-    span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, leaf_tab, occ_tab, nullptr, nullptr);
+    span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, tab, tab, nullptr, nullptr);
     __syncthreads();
-    occ_from_lds<D, LAY>(occ_tab, fd.occ, 1, tid, kServeBlock);
+    occ_from_lds<D, LAY, MASK>(tab, fd.occ, 1, tid, kServeBlock);
 }
 
 template <int MODE>
-__device__ __forceinline__ void serve_dispatch(const ServeFrameDev &fd, int gb, int ge, uint32_t *leaf_tab,
-                                               uint32_t *occ_tab, bool load_leaf) {
+__device__ __forceinline__ void serve_dispatch(const ServeFrameDev &fd, int gb, int ge, uint32_t *tab,
+                                               bool load_leaf) {
     switch (fd.depth) {
-        case 1: serve_part<1, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
-        case 2: serve_part<2, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
-        case 3: serve_part<3, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
-        case 4: serve_part<4, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
-        case 5: serve_part<5, LAY_WIDE, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
-        default: serve_part<6, LAY_COMPACT, MODE>(fd, gb, ge, leaf_tab, occ_tab, load_leaf); break;
+        case 1: serve_part<1, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
+        case 2: serve_part<2, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
+        case 3: serve_part<3, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
+        case 4: serve_part<4, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
+        case 5: serve_part<5, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
+        default: serve_part<6, LAY_COMPACT, MODE>(fd, gb, ge, tab, load_leaf); break;
     }
 }
 
 // Training frames (occupancy) and test frames (mask and occupancy) of a batch
 // in one launch.
 __global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))) void serve_kernel(ServeArgs b) {
-    __shared__ uint32_t leaf_tab[kServeTableWords];
-    __shared__ uint32_t occ_tab[kServeTableWords];
+    __shared__ uint32_t tab[2 * kServeTableWords];
     int64_t g = (int64_t)blockIdx.x * b.chunk;
     const int64_t gend = min(g + b.chunk, b.n_groups);
     if (g >= gend) return;
@@ -128,10 +135,11 @@ __global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))
         const int lb = (int)(g - fd.g0);
         const int le = (int)min<int64_t>(gend - fd.g0, (int64_t)fd.groups);
         if (fd.mask) {
-            serve_dispatch<MODE_MASK | MODE_OCC>(fd, lb, le, leaf_tab, occ_tab, fd.leaf != cur_leaf);
+            serve_dispatch<MODE_MASK | MODE_OCC>(fd, lb, le, tab, fd.leaf != cur_leaf);
             cur_leaf = fd.leaf;
         } else {
-            serve_dispatch<MODE_OCC>(fd, lb, le, leaf_tab, occ_tab, false);
+            serve_dispatch<MODE_OCC>(fd, lb, le, tab, false);
+            cur_leaf = nullptr;   // the table no longer holds a leaf set
         }
         g = fd.g0 + le;
         ++fi;

@@ -14,17 +14,25 @@ namespace obg {
 // From d = 2 on a key word moves as eight nibbles (device.h).
 // native: the bitsets in HBM are already in the compact LDS order (the
 // serving runtime's own rings and leaf sets); words are copied as they are.
-template <int D, int PAD>
+template <int D, int PAD, bool DUAL = false>
 __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, uint32_t *lds,
                                             int n_tiles, int tid, int nt, bool native = false) {
     constexpr int KW = leaf_words(D);
-    constexpr int LW = lds_words(D, PAD);
+    constexpr int LW = lds_words(D, PAD) * (DUAL ? 2 : 1);   // table words per tile
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
+    const uint32_t valid = LC < 32 ? (1u << (LC & 31)) - 1u : 0xFFFFFFFFu;
     if (PAD == LAY_COMPACT && native) {
-        static_assert(PAD != LAY_COMPACT || LW == KW, "compact tables are key-sized");
-        const uint32_t valid = LC < 32 ? (1u << (LC & 31)) - 1u : 0xFFFFFFFFu;
-        for (int i = tid; i < n_tiles * KW; i += nt) lds[i] = leaf[i] & valid;
+        static_assert(PAD != LAY_COMPACT || lds_words(D, PAD) == KW, "compact tables are key-sized");
+        for (int i = tid; i < n_tiles * KW; i += nt) {
+            const uint32_t w = leaf[i] & valid;
+            if (DUAL) {
+                lds[2 * i] = w;
+                lds[2 * i + 1] = 0;
+            } else {
+                lds[i] = w;
+            }
+        }
         __syncthreads();
         return;
     }
@@ -33,20 +41,19 @@ __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, u
     for (int i = tid; i < n_tiles * KW; i += nt) {
         const int c = i / KW;
         const int kw = i - c * KW;
-        uint32_t bits = leaf[i];
-        if (LC < 32) bits &= (1u << (LC & 31)) - 1u;
+        uint32_t bits = leaf[i] & valid;
         if (bits == 0) continue;
         uint32_t *tile = lds + c * LW;
         if constexpr (D >= 2) {
             // eight nibbles per key word
-            key_word_to_table<D, PAD>(bits, (uint32_t)kw, [&](uint32_t w, uint32_t m) { atomicOr(&tile[w], m); });
+            key_word_to_table<D, PAD, DUAL>(bits, (uint32_t)kw, [&](uint32_t w, uint32_t m) { atomicOr(&tile[w], m); });
         } else {
             const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 if ((bits >> b) & 1u) {
                     const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
-                    atomicOr(&tile[l >> 5], 1u << (l & 31));
+                    atomicOr(&tile[DUAL ? 2 * (l >> 5) : (l >> 5)], 1u << (l & 31));
                 }
             }
         }
@@ -54,20 +61,26 @@ __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, u
     __syncthreads();
 }
 
+// Dual tables: clear the occupancy words (the odd ones), keep the leaf words.
+__device__ __forceinline__ void clear_dual_occ(uint32_t *lds, int words, int tid, int nt) {
+    for (int i = 2 * tid + 1; i < words; i += 2 * nt) lds[i] = 0;
+}
+
 // store: every output word belongs to this workgroup alone (one work item per
 // segment), so it is written as is; otherwise set bits are OR-ed into words
 // other workgroups also write.
-template <int D, int PAD>
+template <int D, int PAD, bool DUAL = false>
 __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__restrict__ occ,
                                              int n_tiles, int tid, int nt, bool store = false,
                                              bool native = false) {
     constexpr int KW = leaf_words(D);
-    constexpr int LW = lds_words(D, PAD);
+    constexpr int LW = lds_words(D, PAD) * (DUAL ? 2 : 1);
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
     if (PAD == LAY_COMPACT && native) {
         for (int i = tid; i < n_tiles * KW; i += nt) {
-            const uint32_t w = lds[i];
+            uint32_t w;
+            w = lds[DUAL ? 2 * i + 1 : i];
             if (store)
                 occ[i] = w;
             else if (w)
@@ -81,13 +94,13 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
         const uint32_t *tile = lds + c * LW;
         uint32_t out = 0;
         if constexpr (D >= 2) {
-            out = key_word_from_table<D, PAD>(tile, (uint32_t)kw);
+            out = key_word_from_table<D, PAD, DUAL>(tile, (uint32_t)kw);
         } else {
             const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const uint32_t l = lbase | lds_from_key((uint32_t)b, D, PAD);
-                out |= ((tile[l >> 5] >> (l & 31)) & 1u) << b;
+                out |= ((tile[DUAL ? 2 * (l >> 5) + 1 : (l >> 5)] >> (l & 31)) & 1u) << b;
             }
         }
         if (store)
@@ -154,6 +167,23 @@ __device__ __forceinline__ uint32_t group_pixels(const uint32_t (&u)[12], int nv
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr bool CNT = (MODE & MODE_COUNTS) != 0;
     uint32_t present = 0;
+    if constexpr (MASK && OCC && !CNT) {
+        // dual table (leaf_tile == occ_tile): one 8-byte read gives the
+        // pixel's leaf word and occupancy word; the occupancy bit is set with
+        // an atomic OR only where the word lacks it (the look is free here,
+        // so occ_test does not apply)
+#pragma unroll
+        for (int p = 0; p < 16; ++p) {
+            uint32_t addr, bit;
+            lds_pos<D, PAD>(u, p, addr, bit);
+            const uint2 v = *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(occ_tile) + 2 * addr);
+            const uint32_t m = 1u << (bit & 31);
+            present |= ((v.x >> (bit & 31)) & 1u) << p;
+            if ((!GUARD || p < nvalid) && !(v.y & m))
+                atomicOr(reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(occ_tile) + 2 * addr + 4), m);
+        }
+        return present;
+    }
     uint32_t run_l = 0xFFFFFFFFu, run_n = 0;
 #pragma unroll
     for (int p = 0; p < 16; ++p) {
@@ -202,8 +232,10 @@ __device__ __forceinline__ void consume_group(const StripArgs &a, const Chunk &c
         c = (int)fdiv(gx, a.div_tile) - ch.c0;
         c = c < ch.tiles ? c : ch.tiles - 1;        // padding groups: result discarded
     }
-    const uint32_t *leaf_tile = leaf_lds + c * LW;
-    uint32_t *occ_tile = occ_lds + c * LW;
+    // fused passes keep one dual table per tile (leaf_lds == occ_lds)
+    constexpr int TW = ((MODE & MODE_MASK) && (MODE & MODE_OCC) && !CNT) ? 2 * LW : LW;
+    const uint32_t *leaf_tile = leaf_lds + c * TW;
+    uint32_t *occ_tile = occ_lds + c * TW;
     uint32_t *cnt = CNT ? cbase + (int64_t)c * LC : nullptr;
     uint32_t present;
     if (nv == 16)

@@ -287,7 +287,7 @@ def obg_score(g: FrameGeom, mask: torch.Tensor, truth: torch.Tensor, n_frames: i
 
 TUNE_KEYS = {"train_block": 0, "occ_blind": 1, "occ_wg_per_cu": 2,
              "classify_wg_per_cu": 3, "classify_span": 4, "classify_block": 5, "layout": 6, "interleave": 7, "mask_stage": 8,
-             "region_chunks": 9, "batch_per_depth": 10, "batch_graph": 11}
+             "region_chunks": 9, "batch_per_depth": 10, "batch_graph": 11, "fused_span": 12}
 
 
 def obg_tune_set(key, value: int):

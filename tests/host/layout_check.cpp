@@ -36,6 +36,29 @@ static void check_words(uint64_t seed) {
             });
         for (uint32_t i = 0; i < lw; ++i) CHECK(tab[i] == tab2[i]);
         for (uint32_t kw = 0; kw < kwords; ++kw) CHECK((key_word_from_table<D, LAY>(tab, kw) == key[kw]));
+        // dual tables: word 2w the leaf set's word w, word 2w + 1 the
+        // occupancy's (the other words filled with noise that each direction
+        // must ignore)
+        uint32_t *dt = (uint32_t *)calloc(2 * lw, 4), *dt2 = (uint32_t *)calloc(2 * lw, 4);
+        for (uint32_t k = 0; k < nkeys; ++k) {
+            const uint32_t l = lds_from_key(k, D, LAY);
+            seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
+            if ((key[k >> 5] >> (k & 31)) & 1u) dt[2 * (l >> 5) + 1] |= 1u << (l & 31);   // occupancy
+            if (seed & 1) dt[2 * (l >> 5)] |= 1u << (l & 31);                             // leaf noise
+        }
+        for (uint32_t kw = 0; kw < kwords; ++kw) CHECK((key_word_from_table<D, LAY, true>(dt, kw) == key[kw]));
+        for (uint32_t kw = 0; kw < kwords; ++kw)
+            key_word_to_table<D, LAY, true>(key[kw], kw, [&](uint32_t w, uint32_t m) {
+                CHECK(w < 2 * lw);
+                CHECK(w % 2 == 0);
+                if (w < 2 * lw) dt2[w] |= m;
+            });
+        for (uint32_t k = 0; k < nkeys; ++k) {
+            const uint32_t l = lds_from_key(k, D, LAY);
+            CHECK((((dt2[2 * (l >> 5)] >> (l & 31)) & 1u) == ((key[k >> 5] >> (k & 31)) & 1u)));
+        }
+        free(dt);
+        free(dt2);
     }
     free(key);
     free(tab);
