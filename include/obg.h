@@ -455,7 +455,8 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
  *                               (default), 2 = runs launch them directly
  *   OBG_TUNE_FUSED_SPAN         16-pixel groups per work item of the fused
  *                               classify + occupancy pass without regions
- *                               (0 = the built-in rule)
+ *                               (default 4096; items of at most 4096 groups
+ *                               gather their masks in LDS)
  */
 #define OBG_TUNE_TRAIN_BLOCK         0
 #define OBG_TUNE_OCC_BLIND           1

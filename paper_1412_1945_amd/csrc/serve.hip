@@ -85,7 +85,7 @@ __device__ __forceinline__ int frame_of(const ServeArgs &b, int64_t g) {
 // an occupancy table in the same memory.
 template <int D, int LAY, int MODE>
 __device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, int gb, int ge, uint32_t *tab,
-                                                     bool load_leaf) {
+                                                     uint16_t *stage, bool load_leaf) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr int LW = lds_words(D, LAY);
     const int tid = threadIdx.x;
@@ -103,21 +103,30 @@ __device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, in
     const __amdgpu_buffer_rsrc_t rs = make_rsrc(fd.rgb, (uint32_t)a.frame_pitch);
     __amdgpu_buffer_rsrc_t ms = make_rsrc(nullptr, 0);
     if (MASK) ms = make_rsrc(fd.mask, (uint32_t)a.height * (uint32_t)a.mask_row_words * 8u);
-    span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, tab, tab, nullptr, nullptr);
+    if (MASK) {
+        // masks gathered in LDS and written in runs of up to kFusedStageGroups
+        // groups (frame starts and work splits are multiples of 4 groups, so
+        // every run starts on a 64-pixel mask word)
+        for (int s0 = gb; s0 < ge; s0 += kFusedStageGroups)
+            span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, s0, min(s0 + kFusedStageGroups, ge), tab, tab,
+                                                        nullptr, stage);
+    } else {
+        span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, tab, tab, nullptr, nullptr);
+    }
     __syncthreads();
     occ_from_lds<D, LAY, MASK>(tab, fd.occ, 1, tid, kServeBlock);
 }
 
 template <int MODE>
 __device__ __forceinline__ void serve_dispatch(const ServeFrameDev &fd, int gb, int ge, uint32_t *tab,
-                                               bool load_leaf) {
+                                               uint16_t *stage, bool load_leaf) {
     switch (fd.depth) {
-        case 1: serve_part<1, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
-        case 2: serve_part<2, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
-        case 3: serve_part<3, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
-        case 4: serve_part<4, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
-        case 5: serve_part<5, LAY_WIDE, MODE>(fd, gb, ge, tab, load_leaf); break;
-        default: serve_part<6, LAY_COMPACT, MODE>(fd, gb, ge, tab, load_leaf); break;
+        case 1: serve_part<1, LAY_WIDE, MODE>(fd, gb, ge, tab, stage, load_leaf); break;
+        case 2: serve_part<2, LAY_WIDE, MODE>(fd, gb, ge, tab, stage, load_leaf); break;
+        case 3: serve_part<3, LAY_WIDE, MODE>(fd, gb, ge, tab, stage, load_leaf); break;
+        case 4: serve_part<4, LAY_WIDE, MODE>(fd, gb, ge, tab, stage, load_leaf); break;
+        case 5: serve_part<5, LAY_WIDE, MODE>(fd, gb, ge, tab, stage, load_leaf); break;
+        default: serve_part<6, LAY_COMPACT, MODE>(fd, gb, ge, tab, stage, load_leaf); break;
     }
 }
 
@@ -125,6 +134,7 @@ __device__ __forceinline__ void serve_dispatch(const ServeFrameDev &fd, int gb, 
 // in one launch.
 __global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))) void serve_kernel(ServeArgs b) {
     __shared__ uint32_t tab[2 * kServeTableWords];
+    __shared__ uint16_t stage[kFusedStageGroups];
     int64_t g = (int64_t)blockIdx.x * b.chunk;
     const int64_t gend = min(g + b.chunk, b.n_groups);
     if (g >= gend) return;
@@ -135,10 +145,10 @@ __global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))
         const int lb = (int)(g - fd.g0);
         const int le = (int)min<int64_t>(gend - fd.g0, (int64_t)fd.groups);
         if (fd.mask) {
-            serve_dispatch<MODE_MASK | MODE_OCC>(fd, lb, le, tab, fd.leaf != cur_leaf);
+            serve_dispatch<MODE_MASK | MODE_OCC>(fd, lb, le, tab, stage, fd.leaf != cur_leaf);
             cur_leaf = fd.leaf;
         } else {
-            serve_dispatch<MODE_OCC>(fd, lb, le, tab, false);
+            serve_dispatch<MODE_OCC>(fd, lb, le, tab, nullptr, false);
             cur_leaf = nullptr;   // the table no longer holds a leaf set
         }
         g = fd.g0 + le;

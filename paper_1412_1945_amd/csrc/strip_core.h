@@ -121,7 +121,7 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
 typedef __attribute__((ext_vector_type(4))) unsigned int v4u;
 typedef __attribute__((ext_vector_type(2))) unsigned int v2u;
 
-constexpr int kStageGroups = 1024;
+
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
