@@ -83,11 +83,10 @@ __host__ __device__ inline uint32_t nib_pick(uint32_t w, int off) {
 // a pixel both bits.
 
 // Key word kw of one tree's LDS table (gather of 8 nibbles); DUAL: the
-// occupancy words of a dual table.
+// occupancy words of a dual table.  lbase = lds_from_key(32 kw).
 template <int D, int LAY, bool DUAL = false>
-__host__ __device__ inline uint32_t key_word_from_table(const uint32_t *tab, uint32_t kw) {
+__host__ __device__ inline uint32_t key_word_from_table_at(const uint32_t *tab, uint32_t lbase) {
     static_assert(D >= 2, "a key word holds at least 32 keys from d = 2 on");
-    const uint32_t lbase = lds_from_key(kw << 5, D, LAY);
     uint32_t out = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -98,14 +97,17 @@ __host__ __device__ inline uint32_t key_word_from_table(const uint32_t *tab, uin
     }
     return out;
 }
+template <int D, int LAY, bool DUAL = false>
+__host__ __device__ inline uint32_t key_word_from_table(const uint32_t *tab, uint32_t kw) {
+    return key_word_from_table_at<D, LAY, DUAL>(tab, lds_from_key(kw << 5, D, LAY));
+}
 
 // Key word kw with bits `bits` into one tree's LDS table: or_into(word, mask)
 // is called for each non-empty nibble (8 at most); DUAL: into the leaf words
 // of a dual table.
 template <int D, int LAY, bool DUAL = false, typename OrInto>
-__host__ __device__ inline void key_word_to_table(uint32_t bits, uint32_t kw, OrInto or_into) {
+__host__ __device__ inline void key_word_to_table_at(uint32_t bits, uint32_t lbase, OrInto or_into) {
     static_assert(D >= 2, "a key word holds at least 32 keys from d = 2 on");
-    const uint32_t lbase = lds_from_key(kw << 5, D, LAY);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const uint32_t n = nib_pick(bits, nib_key(q));
@@ -113,6 +115,10 @@ __host__ __device__ inline void key_word_to_table(uint32_t bits, uint32_t kw, Or
         const uint32_t w = (lbase >> 5) + (nl >> 5);
         if (n) or_into(DUAL ? 2 * w : w, n << ((lbase & 31u) + (nl & 31u)));
     }
+}
+template <int D, int LAY, bool DUAL = false, typename OrInto>
+__host__ __device__ inline void key_word_to_table(uint32_t bits, uint32_t kw, OrInto or_into) {
+    key_word_to_table_at<D, LAY, DUAL>(bits, lds_from_key(kw << 5, D, LAY), or_into);
 }
 
 // Exact unsigned division by a runtime-invariant divisor with one high

@@ -9,6 +9,24 @@ namespace obg {
 // ---------------------------------------------------------------------------
 // LDS <-> HBM bitset conversion (key order in HBM, LDS order on chip)
 
+// lds_from_key(32 kw) for the key words a thread visits in the conversion
+// loops below (i = tid, tid + nt, ...; kw = i mod KW).  KW and nt are powers of
+// two, so either every kw of a thread is tid mod KW (nt a multiple of KW) or
+// kw = tid + u with u a multiple of nt, the same in every lane: the map of
+// disjoint bit sets is the OR of their maps, the lane's part is computed once
+// and the uniform part in scalar registers.
+template <int D, int PAD>
+struct KeyWordBase {
+    uint32_t lane;    // lds_from_key(32 (tid mod KW))
+    int tmod;
+    __device__ __forceinline__ KeyWordBase(int tid, int kwords)
+        : lane(lds_from_key((uint32_t)(tid % kwords) << 5, D, PAD)), tmod(tid % kwords) {}
+    __device__ __forceinline__ uint32_t operator()(int kw) const {
+        const uint32_t u = (uint32_t)__builtin_amdgcn_readfirstlane(kw - tmod);
+        return lane | lds_from_key(u << 5, D, PAD);
+    }
+};
+
 // The bits of one key-order word kw are keys 32*kw + b; their LDS indices are
 // lds_from_key(32*kw) | lds_from_key(b) because the map permutes index bits.
 // From d = 2 on a key word moves as eight nibbles (device.h).
@@ -38,16 +56,18 @@ __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, u
     }
     for (int i = tid; i < n_tiles * LW; i += nt) lds[i] = 0;
     __syncthreads();
+    const KeyWordBase<D, PAD> kbase(tid, KW);
     for (int i = tid; i < n_tiles * KW; i += nt) {
         const int c = i / KW;
         const int kw = i - c * KW;
         uint32_t bits = leaf[i] & valid;
-        if (bits == 0) continue;
         uint32_t *tile = lds + c * LW;
         if constexpr (D >= 2) {
             // eight nibbles per key word
-            key_word_to_table<D, PAD, DUAL>(bits, (uint32_t)kw, [&](uint32_t w, uint32_t m) { atomicOr(&tile[w], m); });
+            const uint32_t lbase = kbase(kw);
+            if (bits) key_word_to_table_at<D, PAD, DUAL>(bits, lbase, [&](uint32_t w, uint32_t m) { atomicOr(&tile[w], m); });
         } else {
+            if (bits == 0) continue;
             const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
@@ -88,13 +108,14 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
         }
         return;
     }
+    const KeyWordBase<D, PAD> kbase(tid, KW);
     for (int i = tid; i < n_tiles * KW; i += nt) {
         const int c = i / KW;
         const int kw = i - c * KW;
         const uint32_t *tile = lds + c * LW;
         uint32_t out = 0;
         if constexpr (D >= 2) {
-            out = key_word_from_table<D, PAD, DUAL>(tile, (uint32_t)kw);
+            out = key_word_from_table_at<D, PAD, DUAL>(tile, kbase(kw));
         } else {
             const uint32_t lbase = lds_from_key((uint32_t)kw << 5, D, PAD);
 #pragma unroll

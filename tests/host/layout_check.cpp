@@ -66,6 +66,24 @@ static void check_words(uint64_t seed) {
 }
 
 int main() {
+    // the conversion loops' split of lds_from_key(32 kw) into a lane part
+    // (tid mod KW) and a part common to a wave's lanes (kw - tid mod KW)
+    for (int lay = 0; lay < 2; ++lay)
+        for (int d = 2; d <= (lay == LAY_WIDE ? 5 : 6); ++d) {
+            const int kwords = 1 << (3 * d - 5);
+            for (int nt = 256; nt <= 1024; nt *= 2)
+                for (int tid = 0; tid < nt; tid += 7)
+                    for (int i = tid; i < 4 * kwords; i += nt) {
+                        const int kw = i % kwords, t = tid % kwords;
+                        const int u = kw - t;
+                        CHECK(u >= 0);
+                        CHECK(((u & t) == 0));
+                        CHECK((lds_from_key((uint32_t)t << 5, d, lay) | lds_from_key((uint32_t)u << 5, d, lay)) ==
+                              lds_from_key((uint32_t)kw << 5, d, lay));
+                        if (kwords < nt) CHECK(u == 0);
+                        if (kwords >= nt) CHECK(u == (i - tid) % kwords);   // the same for every lane of the step
+                    }
+        }
     check_words<2, LAY_WIDE>(1); check_words<3, LAY_WIDE>(2); check_words<4, LAY_WIDE>(3);
     check_words<5, LAY_WIDE>(4);
     check_words<2, LAY_COMPACT>(5); check_words<3, LAY_COMPACT>(6); check_words<4, LAY_COMPACT>(7);
