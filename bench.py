@@ -58,6 +58,9 @@ def parse():
                    help="HBM traffic of the classify kernel measured with rocprofv3 counters")
     p.add_argument("--probe", action="store_true",
                    help="only run the streaming probes (read, read+write, 1 GiB copy) and print them")
+    p.add_argument("--knob-sweep", action="store_true",
+                   help="only time classify and the fused classify + occupancy pass on 1000 frames of the 1080p "
+                        "workload over their launch knobs (every setting checked against the default's output)")
     p.add_argument("--probe-sweep", action="store_true",
                    help="only sweep the shaped read and read+write probes over 1000 frames' bytes of the 1080p "
                         "workload (grid, block, groups in flight, item size, phased writes) and print the table")
@@ -152,6 +155,74 @@ def probe_sweep(reps=3):
             for k in (obg.PROBE_READ, obg.PROBE_READ_WRITE)}
     print(json.dumps({"probe_sweep": rows, "bytes": nbytes, "best_read": best[obg.PROBE_READ],
                       "best_read_write": best[obg.PROBE_READ_WRITE]}), flush=True)
+
+
+def knob_sweep(reps=5):
+    """Classify and the fused pass (classify + each frame's tree) on 1000 test
+    frames of the 1080p d=5 stream, over their launch knobs.  The leaf set is
+    the merged one with every other word cleared, so the masks hold both
+    classes; every setting's outputs must equal the default's."""
+    import itertools
+    import torch
+    from paper_1412_1945_amd import obg
+    from synth import frames as S
+    from synth.fast import make_frames_gpu
+    obg.load()
+    wl = S.cfg1(n_test=1000)
+    spec, d, (num, den) = wl.streams[0], wl.depth[0], wl.thr[0]
+    g = obg.FrameGeom(spec.width, spec.height, d)
+    T, N = spec.n_train, spec.n_test
+    fr = torch.empty((T + N, spec.height, spec.row_pitch), dtype=torch.uint8, device="cuda")
+    for i in range(0, T + N, 100):
+        ids = list(range(i, min(T + N, i + 100)))
+        make_frames_gpu(spec, ids, fr[ids[0]: ids[-1] + 1])
+    occ, leaf = obg.empty_occ(g, T), obg.empty_leafset(g)
+    obg.obg_train_frame(g, fr[:T], T, occ)
+    obg.obg_merge(g, occ, T, 0, T, num, den, leaf)
+    leaf[:, ::2] = 0
+    test = fr[T:]
+    ref_m, ref_o = obg.empty_mask(g, N), obg.empty_occ(g, N)
+    obg.obg_classify(g, test, N, leaf, ref_m, ref_o)
+    mask, occ_out = obg.empty_mask(g, N), obg.empty_occ(g, N)
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    nbytes = N * spec.pixels * 3 + N * spec.height * g.mask_row_words * 8
+
+    def run(knobs, fused):
+        for k, v in knobs.items():
+            obg.obg_tune_set(k, v)
+        ts = []
+        for r in range(reps + 1):
+            a, b = ev(), ev()
+            a.record()
+            obg.obg_classify(g, test, N, leaf, mask, occ_out if fused else None)
+            b.record()
+            torch.cuda.synchronize()
+            if r:
+                ts.append(a.elapsed_time(b))
+        for k in knobs:
+            obg.obg_tune_set(k, 0)
+        same = torch.equal(mask, ref_m) and (not fused or torch.equal(occ_out, ref_o))
+        ms = sorted(ts)[len(ts) // 2]
+        extra = N * g.words * 4 if fused else 0
+        row = dict(knobs, pass_="fused" if fused else "classify", med_ms=round(ms, 4),
+                   tb_s=round((nbytes + extra) / (ms * 1e-3) / 1e12, 3), same=same)
+        print(f"# {row}", file=sys.stderr, flush=True)
+        return row
+
+    rows = []
+    for block, wpc, span, inter, stage in itertools.product((256, 512), (1, 2, 3, 4), (512, 832, 1024, 1664),
+                                                            (1, 2), (1, 2)):
+        if block == 512 and wpc > 2:
+            continue
+        rows.append(run(dict(classify_block=block, classify_wg_per_cu=wpc, classify_span=span, interleave=inter,
+                             mask_stage=stage), False))
+    for layout, wpc, span, inter, stage in itertools.product((1, 2), (2, 4), (1024, 2048, 4096, 8192, 32768),
+                                                             (1, 2), (1, 2)):
+        if layout == 1 and wpc == 4:
+            continue
+        rows.append(run(dict(layout=layout, occ_wg_per_cu=wpc, fused_span=span, interleave=inter, mask_stage=stage),
+                        True))
+    print(json.dumps({"knob_sweep": rows}), flush=True)
 
 
 def workload(name, n_test):
@@ -635,6 +706,8 @@ def main():
         return run_served(a)
     if a.probe_sweep:
         return probe_sweep()
+    if a.knob_sweep:
+        return knob_sweep()
     import torch
     from paper_1412_1945_amd import obg
     from synth.frames import make_frames
