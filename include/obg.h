@@ -373,8 +373,9 @@ typedef struct obg_serve_config {
     /* Checkpoint, NULLABLE (host buffers of obg_serve_state_bytes bytes).
        state_out receives, when the run ends, every stream's merged leaf set,
        its ring of per-frame trees and the index of its next frame (region
-       streams may hold their bitsets in the kernels' own bit order, which
-       the stream's record names: a state is for restoring, not for reading;
+       streams and streams of depth 5 or 6 may hold their bitsets in the
+       kernels' own bit order, which the stream's record names: a state is
+       for restoring, not for reading;
        a state restored under an OBG_TUNE_LAYOUT setting that picks the other
        order for a stream is refused with OBG_EINVAL).  state_in
        restores such a state (written for the same streams: geometry, depth,

@@ -41,7 +41,8 @@ struct ServeFrameDev {
     uint32_t *occ;            // ring slot of this frame
     uint32_t *leaf;           // the stream's merged leaf set (test frames)
     uint64_t *mask;           // test frames; NULL for training frames
-    int32_t depth, groups, words, pad_;
+    int32_t depth, groups, words;
+    int32_t native;           // ring slot and leaf set in the LDS order (d = 5, 6)
     int64_t g0;               // first group of the frame in the batch's group space
 };
 
@@ -93,7 +94,7 @@ __device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, in
     __syncthreads();   // the previous part's flush has read the table
     if (MASK) {
         if (load_leaf)
-            leaf_to_lds<D, LAY, true>(fd.leaf, tab, 1, tid, kServeBlock);
+            leaf_to_lds<D, LAY, true>(fd.leaf, tab, 1, tid, kServeBlock, fd.native != 0);
         else
             clear_dual_occ(tab, 2 * LW, tid, kServeBlock);
     } else {
@@ -114,7 +115,7 @@ __device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, in
         span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, tab, tab, nullptr, nullptr);
     }
     __syncthreads();
-    occ_from_lds<D, LAY, MASK>(tab, fd.occ, 1, tid, kServeBlock);
+    occ_from_lds<D, LAY, MASK>(tab, fd.occ, 1, tid, kServeBlock, false, fd.native != 0);
 }
 
 template <int MODE>
@@ -201,7 +202,7 @@ struct StreamDev {
     int words = 0, valid_bits = 32, groups = 0;
     int n_regions = 1;
     bool region = false;      // one tree per region: the region passes serve it
-    bool native = false;      // region rings and leaf set kept in the compact LDS order
+    bool native = false;      // rings and leaf set kept in the LDS order
     obg_geom geom{};          // for those passes
 };
 
@@ -265,8 +266,9 @@ struct StateHeader {
     int32_t n_streams, window;
 };
 struct StateStream {
-    // order: 0 = bitsets in key order, 1 = region bitsets in the compact LDS
-    // order (the stream's passes all run with compact tables)
+    // order: 0 = bitsets in key order, 1 = in the LDS order of the stream's
+    // passes (region streams whose passes all run with compact tables; streams
+    // without regions at d = 5 and 6)
     int32_t width, height, depth, n_train, region_w, region_h, ring_len, order;
     int64_t next_frame;
     uint64_t tree_bytes;
@@ -350,11 +352,15 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         sd.geom.depth = c.depth;
         sd.geom.region_w = c.region_w;
         sd.geom.region_h = c.region_h;
-        // the rings and leaf set of a region stream never leave the library:
-        // where every pass of the stream runs over frame lists with compact
-        // tables they stay in that order, and the flushes and table loads
-        // copy words (merges count bit by bit, whatever the order)
-        sd.native = sd.region && pixels_list_native_ok(&sd.geom);
+        // a stream's rings and leaf set never leave the library: where every
+        // pass of the stream keeps its tables in one LDS order they stay in
+        // that order, and the flushes and table loads copy words (merges
+        // count bit by bit, whatever the order).  Region streams: passes over
+        // frame lists with compact tables.  Streams without regions at
+        // d = 5 (wide tables, word G'<<5 | R') and d = 6 (compact tables):
+        // serve_kernel, where converting the 1024 or 8192 key words of a
+        // table at every load and flush costs more than small frames' pixels
+        sd.native = sd.region ? pixels_list_native_ok(&sd.geom) : (c.depth == 5 || c.depth == 6);
         StripArgs &a = sd.a;
         a.width = c.width;
         a.height = c.height;
@@ -587,7 +593,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 fd.depth = sd.cfg.depth;
                 fd.groups = sd.region ? 0 : sd.groups;
                 fd.words = sd.words;
-                fd.pad_ = 0;
+                fd.native = sd.native ? 1 : 0;
                 fd.g0 = n_groups;
                 n_groups += fd.groups;
                 sl.arrival[p] = cfg->arrivals[fr.stream][fr.frame - first[fr.stream]] / cfg->speed;

@@ -30,8 +30,16 @@ struct KeyWordBase {
 // The bits of one key-order word kw are keys 32*kw + b; their LDS indices are
 // lds_from_key(32*kw) | lds_from_key(b) because the map permutes index bits.
 // From d = 2 on a key word moves as eight nibbles (device.h).
-// native: the bitsets in HBM are already in the compact LDS order (the
-// serving runtime's own rings and leaf sets); words are copied as they are.
+// native: the bitsets in HBM are already in the LDS order (the serving
+// runtime's own rings and leaf sets): compact tables copy words as they are,
+// wide tables at d = 5 copy word n = G'<<5 | R' to LDS word G'<<8 | R'.
+template <int D, int PAD>
+__device__ __forceinline__ constexpr bool native_order_ok() { return PAD == LAY_COMPACT || D == 5; }
+template <int D, int PAD>
+__device__ __forceinline__ int native_word(int n) {
+    return PAD == LAY_COMPACT ? n : (((n >> 5) << 8) | (n & 31));
+}
+
 template <int D, int PAD, bool DUAL = false>
 __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, uint32_t *lds,
                                             int n_tiles, int tid, int nt, bool native = false) {
@@ -40,15 +48,17 @@ __device__ __forceinline__ void leaf_to_lds(const uint32_t *__restrict__ leaf, u
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
     const uint32_t valid = LC < 32 ? (1u << (LC & 31)) - 1u : 0xFFFFFFFFu;
-    if (PAD == LAY_COMPACT && native) {
+    if (native_order_ok<D, PAD>() && native) {
         static_assert(PAD != LAY_COMPACT || lds_words(D, PAD) == KW, "compact tables are key-sized");
         for (int i = tid; i < n_tiles * KW; i += nt) {
+            const int c = i / KW;
             const uint32_t w = leaf[i] & valid;
+            const int l = c * LW + (DUAL ? 2 : 1) * native_word<D, PAD>(i - c * KW);
             if (DUAL) {
-                lds[2 * i] = w;
-                lds[2 * i + 1] = 0;
+                lds[l] = w;
+                lds[l + 1] = 0;
             } else {
-                lds[i] = w;
+                lds[l] = w;
             }
         }
         __syncthreads();
@@ -97,10 +107,11 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
     constexpr int LW = lds_words(D, PAD) * (DUAL ? 2 : 1);
     constexpr int LC = leaf_count(D);
     constexpr int NB = LC < 32 ? LC : 32;
-    if (PAD == LAY_COMPACT && native) {
+    if (native_order_ok<D, PAD>() && native) {
         for (int i = tid; i < n_tiles * KW; i += nt) {
-            uint32_t w;
-            w = lds[DUAL ? 2 * i + 1 : i];
+            const int c = i / KW;
+            const int l = c * LW + (DUAL ? 2 : 1) * native_word<D, PAD>(i - c * KW);
+            const uint32_t w = lds[DUAL ? l + 1 : l];
             if (store)
                 occ[i] = w;
             else if (w)
