@@ -417,11 +417,12 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
  *                               region work items of fewer than 2048
  *                               16-pixel groups)
  *   OBG_TUNE_OCC_BLIND          1 = set occupancy bits with an unconditional
- *                               LDS atomic OR (default at d = 6 and for
- *                               occupancy-only passes with regions), 2 = read
- *                               the word first and OR only a clear bit
- *                               (default otherwise: fewer colliding atomics
- *                               when many pixels share a key)
+ *                               LDS atomic OR (default for occupancy-only
+ *                               passes with regions and for batched trees at
+ *                               d = 6), 2 = read the word first and OR only a
+ *                               clear bit (default otherwise: fewer colliding
+ *                               atomics when many pixels share a key); the
+ *                               fused pass always reads first
  *   OBG_TUNE_OCC_WG_PER_CU      workgroups per CU of passes that build
  *                               occupancy (default 2 at 1024 threads, else 4)
  *   OBG_TUNE_CLASSIFY_WG_PER_CU workgroups per CU of classify-only passes

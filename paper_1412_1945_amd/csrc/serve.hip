@@ -374,7 +374,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         a.n_regions = 1;
         a.div_gpr = make_fastdiv((uint32_t)a.gpr);
         a.div_tile = make_fastdiv((uint32_t)a.gpr);
-        a.occ_test = tune(OBG_TUNE_OCC_BLIND, c.depth <= 5 ? 2 : 1) == 2;
+        a.occ_test = tune(OBG_TUNE_OCC_BLIND, 2) == 2;
         a.mask_row_words = (c.width + 63) / 64;
         sd.groups = c.height * a.gpr;
         sd.words = leaf_words(c.depth);

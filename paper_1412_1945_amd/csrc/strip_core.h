@@ -349,8 +349,33 @@ __device__ __forceinline__ uint32_t merge_word(const uint32_t *__restrict__ ring
 #pragma unroll
     for (int b = 0; b < 16; ++b) c[b] = 0;
     const int n_groups = (n_trees + group - 1) / group;
-    // eight groups per round: their loads are independent and in flight together
-    for (int j0 = 0; j0 < n_groups; j0 += 8) {
+    if (group == 1) {
+        // one tree per slot: sixteen loads per round, independent and in
+        // flight together (a merge is a few dependent rounds of HBM latency)
+        for (int j0 = 0; j0 < n_trees; j0 += 16) {
+            uint32_t x[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                int sl = first + j0 + k;
+                if (sl >= ring_len) sl -= ring_len;
+                x[k] = (j0 + k < n_trees) ? (ring[(int64_t)sl * slot_words + i] & valid) : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                uint32_t carry = x[k];
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    if (b < planes) {
+                        const uint32_t tmp = c[b] & carry;
+                        c[b] ^= carry;
+                        carry = tmp;
+                    }
+                }
+            }
+        }
+    }
+    // groups of frames: eight groups per round, their loads in flight together
+    for (int j0 = 0; group > 1 && j0 < n_groups; j0 += 8) {
         uint32_t x[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
