@@ -283,7 +283,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         store = true;
     } else if ((mode & MODE_MASK) && (mode & MODE_OCC) && g.reg_cols == 1) {
         // fused classify + occupancy without regions: items of at most
-        // kFusedStageGroups groups, whose masks are staged in LDS and written
+        // kMaxStageGroups groups, whose masks are staged in LDS and written
         // as one run each; a segment's occupancy flush is 1024 words at d = 5
         // against 4096 x 16 pixels (measured on 1000 frames of the 1080p
         // stream: 1.35 ms against 1.44 ms for two whole frames per workgroup
@@ -291,7 +291,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
         int want = tune(OBG_TUNE_OCC_WG_PER_CU, 4);
         if (want > per_cu) want = per_cu;
         target = (int64_t)cus * want;
-        const int64_t fspan = tune(OBG_TUNE_FUSED_SPAN, kFusedStageGroups);
+        const int64_t fspan = tune(OBG_TUNE_FUSED_SPAN, kMaxStageGroups);
         spans = (groups_strip + fspan - 1) / fspan;
     } else if (mode & MODE_OCC) {
         // each (frame, strip) segment of a workgroup costs one LDS flush:
@@ -339,7 +339,7 @@ int run_pixels(const Geo &g, int mode, const uint8_t *rgb, int32_t n_frames, con
                        : (tune(OBG_TUNE_INTERLEAVE, 2) == 1);
     // staging writes an item's mask as one run: whole rows only
     const bool fused_plain = (mode & MODE_MASK) && (mode & MODE_OCC) && !(mode & MODE_COUNTS) && g.reg_cols == 1;
-    a.stage_mask = ((mode & MODE_MASK) && span <= (fused_plain ? kFusedStageGroups : kStageGroups) && a.n_chunks == 1)
+    a.stage_mask = ((mode & MODE_MASK) && span <= (fused_plain ? kMaxStageGroups : kStageGroups) && a.n_chunks == 1)
                        ? (tune(OBG_TUNE_MASK_STAGE, 1) == 1)
                        : 0;
     a.occ_store = store ? 1 : 0;

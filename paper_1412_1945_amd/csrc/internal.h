@@ -32,7 +32,7 @@ struct StripArgs {
     int32_t spans;            // work items per (strip, frame)
     int32_t n_items;          // n_strips * n_frames * spans
     int32_t interleave;       // 1: item i goes to workgroup i % grid; 0: contiguous ranges
-    int32_t stage_mask;       // 1: masks gathered in LDS per item (span <= kStageGroups or kFusedStageGroups)
+    int32_t stage_mask;       // 1: masks gathered in LDS per item (span <= kStageGroups or kMaxStageGroups)
     int32_t occ_test;         // 1: read an occupancy word first, atomic OR only when the bit is clear
     int32_t occ_store;        // 1: one work item per (frame, strip): occupancy words are stored, not OR-ed
     const uint32_t *leaf;     // [n_regions][words], key order
@@ -79,10 +79,10 @@ struct MergeArgs {
 enum StripMode { MODE_MASK = 1, MODE_OCC = 2, MODE_COUNTS = 4 };
 
 // Mask staging: a work item of at most this many 16-pixel groups gathers its
-// mask in LDS and writes it as one run; the fused pass without regions stages
-// items of up to kFusedStageGroups.
+// mask in LDS and writes it as one run; the fused pass without regions and
+// the served form stage items of up to kMaxStageGroups.
 constexpr int kStageGroups = 1024;
-constexpr int kFusedStageGroups = 4096;
+constexpr int kMaxStageGroups = 4096;
 
 // Record the calling thread's last error (read by obg_last_error); returns code.
 int set_error(int code, const char *msg);

@@ -52,8 +52,8 @@ strip_kernel(StripArgs a) {
     __shared__ uint32_t st_leaf[(!REGION && MASK) ? (DUAL ? 2 * LW : LW) : 1];
     __shared__ uint32_t st_occ[(!REGION && OCC && !DUAL) ? LW : 1];
     // mask staging: one work item's 16-bit group masks (spans <= kStageGroups,
-    // kFusedStageGroups for the fused pass without regions)
-    __shared__ uint16_t st_mask[MASK ? ((DUAL && !REGION) ? kFusedStageGroups : kStageGroups) : 4];
+    // kMaxStageGroups for the fused pass without regions)
+    __shared__ uint16_t st_mask[MASK ? ((DUAL && !REGION) ? kMaxStageGroups : kStageGroups) : 4];
     uint16_t *stage = (MASK && a.stage_mask) ? st_mask : nullptr;
     const int tid = threadIdx.x;
     // LDS tables of one strip: a chunk of at most chunk_cols regions

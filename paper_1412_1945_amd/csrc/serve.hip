@@ -105,11 +105,11 @@ __device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, in
     __amdgpu_buffer_rsrc_t ms = make_rsrc(nullptr, 0);
     if (MASK) ms = make_rsrc(fd.mask, (uint32_t)a.height * (uint32_t)a.mask_row_words * 8u);
     if (MASK) {
-        // masks gathered in LDS and written in runs of up to kFusedStageGroups
+        // masks gathered in LDS and written in runs of up to kMaxStageGroups
         // groups (frame starts and work splits are multiples of 4 groups, so
         // every run starts on a 64-pixel mask word)
-        for (int s0 = gb; s0 < ge; s0 += kFusedStageGroups)
-            span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, s0, min(s0 + kFusedStageGroups, ge), tab, tab,
+        for (int s0 = gb; s0 < ge; s0 += kMaxStageGroups)
+            span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, s0, min(s0 + kMaxStageGroups, ge), tab, tab,
                                                         nullptr, stage);
     } else {
         span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, tab, tab, nullptr, nullptr);
@@ -135,7 +135,7 @@ __device__ __forceinline__ void serve_dispatch(const ServeFrameDev &fd, int gb, 
 // in one launch.
 __global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))) void serve_kernel(ServeArgs b) {
     __shared__ uint32_t tab[2 * kServeTableWords];
-    __shared__ uint16_t stage[kFusedStageGroups];
+    __shared__ uint16_t stage[kMaxStageGroups];
     int64_t g = (int64_t)blockIdx.x * b.chunk;
     const int64_t gend = min(g + b.chunk, b.n_groups);
     if (g >= gend) return;
