@@ -275,6 +275,58 @@ def test_fused_classify_occupancy(env):
         assert torch.equal(occ_t, occ_c)
 
 
+FUSED_KNOBS = [{}, {"fused_span": 4}, {"fused_span": 100}, {"fused_span": 8192}, {"fused_span": 4, "interleave": 1},
+               {"mask_stage": 2}, {"layout": 2, "occ_wg_per_cu": 4}, {"occ_blind": 1}]
+
+
+@pytest.mark.parametrize("knobs", FUSED_KNOBS,
+                         ids=[",".join(f"{k}={v}" for k, v in kn.items()) or "default" for kn in FUSED_KNOBS])
+def test_fused_knobs_against_oracle(env, knobs):
+    """The fused pass (masks and each test frame's tree from one read, dual
+    LDS tables, staged masks) under its launch knobs: items of 4 groups (many
+    per frame, trees ORed into zeroed words), of a size that is not a multiple
+    of 4, larger than the staging limit, dealt round-robin, and the compact
+    table order.  Masks and trees equal the oracle's, frame by frame."""
+    obg, O = env
+    rng = np.random.default_rng(5150)
+    try:
+        for k, v in knobs.items():
+            obg.obg_tune_set(k, v)
+        for W, H, d in [(200, 30, 3), (333, 17, 5), (130, 26, 6), (64, 8, 4)]:
+            rp = ((3 * W + 15) // 16) * 16
+            T, N = 3, 4
+            frames = brute.tiny_frames(rng, T + N, W, H, n_colours=13, row_pitch=rp)
+            # the right half of every test frame from another palette: both classes
+            other = brute.tiny_frames(rng, N, W, H, n_colours=13, row_pitch=rp)
+            half = 3 * (W // 2)
+            for i in range(N):
+                frames[T + i][:, half:] = other[i][:, half:]
+            g = obg.FrameGeom(W, H, d)
+            print(f"[case] fused knobs {knobs} W={W} H={H} d={d}", flush=True)
+            dtrain, dtest = upload(frames[:T], g.frame_pitch), upload(frames[T:], g.frame_pitch)
+            occ_t, leaf = obg.empty_occ(g, T), obg.empty_leafset(g)
+            obg.obg_train_frame(g, dtrain, T, occ_t)
+            obg.obg_merge(g, occ_t, T, 0, T, 1, 2, leaf)
+            mask = obg.empty_mask(g, N).fill_(-1)
+            occ = obg.empty_occ(g, N).fill_(-1)
+            obg.obg_classify(g, dtest, N, leaf, mask, occ)
+            torch.cuda.synchronize()
+            f = O.Forest(W, H, d)
+            model = f.merge(f.add_frames(frames[:T]), 1, 2)
+            tests = f.add_frames(frames[T:])
+            fg = 0
+            for i in range(N):
+                want = model.classify(frames[T + i])
+                assert np.array_equal(u64(mask[i]).reshape(want.shape), want), f"fused {knobs} mask {i} d={d}"
+                fg += int(np.unpackbits(want.view(np.uint8)).sum())
+                o = f.export(tests[i])
+                assert np.array_equal(u32(occ[i]).reshape(o.shape), o), f"fused {knobs} tree {i} d={d}"
+            assert 0 < fg < N * W * H, "masks hold both classes"
+    finally:
+        for k in obg.TUNE_KEYS:
+            obg.obg_tune_set(k, 0)
+
+
 @pytest.mark.parametrize("W,H,d,rw,rh", [(1280, 720, 4, 32, 32), (1000, 200, 5, 48, 40), (1010, 64, 3, 16, 16),
                                          (3840, 64, 4, 32, 32), (640, 96, 6, 32, 32), (1920, 128, 5, 64, 64)])
 def test_region_chunks_one_frame_per_call(env, W, H, d, rw, rh):
