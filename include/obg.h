@@ -450,9 +450,9 @@ int64_t obg_serve_state_bytes(const obg_serve_stream *streams, int32_t n_streams
  *                               stored (default); 2 = chunks only where a
  *                               row's tables do not fit in LDS
  *   OBG_TUNE_BATCH_PER_DEPTH    shape a plan starts from (obg_plan_create,
- *                               before any tuning): 1 = one persistent
- *                               launch per phase (default), 2 = one launch
- *                               per depth present and phase
+ *                               before any tuning, and obg_batch_run_noalloc):
+ *                               1 = one persistent launch per phase, 2 = one
+ *                               launch per depth present and phase (default)
  *   OBG_TUNE_BATCH_GRAPH        1 = plans capture their steps in a HIP graph
  *                               (default), 2 = runs launch them directly
  *   OBG_TUNE_FUSED_SPAN         16-pixel groups per work item of the fused

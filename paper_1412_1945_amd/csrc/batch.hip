@@ -53,6 +53,7 @@ struct BatchStreamDev {
     int32_t groups;           // 16-pixel groups per frame: height * gpr
     int32_t tspans, tspan;    // training frames: items per frame, groups per item
     int32_t cspans, cspan;    // test frames
+    FastDiv div_tspans, div_cspans;
     int32_t words, valid_bits;
     uint32_t thr_num, thr_den;
     int32_t max_train, max_test;
@@ -76,18 +77,10 @@ struct BatchArgs {
 
 // Item `it` belongs to the last slot whose first item is <= it (a slot
 // without items has the first item of the next slot, so that slot is never
-// the answer).  A workgroup's next item is nearly always in the slot of its
-// last one (`hint`), which is checked first: the search is a chain of
-// dependent loads that would cost about as much as streaming a small item.
+// the answer).
 template <int MODE>
-__device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it, int hint = -1) {
+__device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
-    if (hint >= 0) {
-        const BatchStreamDev &h = b.streams[hint];
-        const int64_t first = MASK ? h.citem0 : h.titem0;
-        const int64_t n = MASK ? (int64_t)h.cspans * h.n_test : (int64_t)h.tspans * h.n_train;
-        if (it >= first && it < first + n) return hint;
-    }
     int lo = 0, hi = b.n_streams - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -100,48 +93,89 @@ __device__ __forceinline__ int stream_of(const BatchArgs &b, int64_t it, int hin
     return lo;
 }
 
-// Work item `local` of stream sd: the frame and the groups it covers.  A
+// What a work item needs of its stream, read once when a workgroup's items
+// reach the stream and kept in registers while they stay on it (items are
+// numbered stream by stream, so a workgroup's next item is nearly always in
+// the stream of its last one).  Reading the slot again for every item puts a
+// chain of dependent loads between the items, which for the classify items of
+// one 1080p stream cost about a third of the time.
+struct ItemStream {
+    StripArgs a;                  // geometry (only the pixel code's fields are kept)
+    int64_t first, count;         // the stream's items in this launch: [first, first + count)
+    FastDiv div_spans;            // divides by the items per frame
+    int32_t spans, span, groups, words;
+    int32_t single;               // one item per training frame: its tree is stored whole
+    const uint8_t *rgb;
+    uint64_t *mask;
+    uint32_t *occ;
+    const uint32_t *leaf;
+};
+
+template <int MODE>
+__device__ __forceinline__ ItemStream load_stream(const BatchStreamDev &sd) {
+    constexpr bool MASK = (MODE & MODE_MASK) != 0;
+    ItemStream c;
+    c.a = sd.a;
+    c.first = MASK ? sd.citem0 : sd.titem0;
+    c.count = MASK ? (int64_t)sd.cspans * sd.n_test : (int64_t)sd.tspans * sd.n_train;
+    c.div_spans = MASK ? sd.div_cspans : sd.div_tspans;
+    c.spans = MASK ? sd.cspans : sd.tspans;
+    c.span = MASK ? sd.cspan : sd.tspan;
+    c.groups = sd.groups;
+    c.words = sd.words;
+    c.single = sd.tspans == 1;
+    c.rgb = MASK ? sd.test_rgb : sd.train_rgb;
+    c.mask = sd.mask;
+    c.occ = sd.occ;
+    c.leaf = sd.leaf;
+    return c;
+}
+
+// Work item `local` of stream cs: the frame and the groups it covers.  A
 // training frame that is one item writes its tree with plain stores; frames
 // cut into several items OR their words into a zeroed tree.
 template <int D, int LAY, int MODE, int BLOCK>
-__device__ __forceinline__ void item_body(const BatchArgs &b, const BatchStreamDev &sd, int64_t local,
+__device__ __forceinline__ void item_body(const BatchArgs &b, const ItemStream &cs, int64_t local,
                                           uint32_t *tab, uint16_t *st_mask, bool new_stream) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     constexpr bool OCC = (MODE & MODE_OCC) != 0;
     constexpr int LW = lds_words(D, LAY);
     const int tid = threadIdx.x;
-    const StripArgs a = sd.a;
-    const int spans = MASK ? sd.cspans : sd.tspans;
-    const int span = MASK ? sd.cspan : sd.tspan;
-    const int f = (int)(local / spans);
-    const int t = (int)(local - (int64_t)f * spans);
+    const StripArgs &a = cs.a;
+    int f, t;
+    if (local <= 0xFFFFFFFFll) {
+        f = (int)fdiv((uint32_t)local, cs.div_spans);
+        t = (int)((uint32_t)local - (uint32_t)f * (uint32_t)cs.spans);
+    } else {
+        f = (int)(local / cs.spans);
+        t = (int)(local - (int64_t)f * cs.spans);
+    }
     if (MASK && new_stream) {
         __syncthreads();
-        leaf_to_lds<D, LAY>(sd.leaf, tab, 1, tid, BLOCK);
+        leaf_to_lds<D, LAY>(cs.leaf, tab, 1, tid, BLOCK);
     }
     if (OCC) {
         __syncthreads();
         for (int i = tid; i < LW; i += BLOCK) tab[i] = 0;
         __syncthreads();
     }
-    const int gb = t * span;
-    const int ge = min(gb + span, sd.groups);
-    const uint8_t *rgb = MASK ? sd.test_rgb : sd.train_rgb;
-    const __amdgpu_buffer_rsrc_t rs = make_rsrc(rgb + (int64_t)f * a.frame_pitch, (uint32_t)a.frame_pitch);
+    const int gb = t * cs.span;
+    const int ge = min(gb + cs.span, cs.groups);
+    const __amdgpu_buffer_rsrc_t rs = make_rsrc(cs.rgb + (int64_t)f * a.frame_pitch, (uint32_t)a.frame_pitch);
     __amdgpu_buffer_rsrc_t ms = make_rsrc(nullptr, 0);
     if (MASK)
-        ms = make_rsrc(sd.mask + (int64_t)f * a.height * a.mask_row_words,
+        ms = make_rsrc(cs.mask + (int64_t)f * a.height * a.mask_row_words,
                        (uint32_t)a.height * (uint32_t)a.mask_row_words * 8u);
     uint16_t *stage = (MASK && b.stage_mask) ? st_mask : nullptr;
     span_loop<D, MODE, LAY, false, BLOCK>(a, rs, ms, gb, ge, tab, tab, nullptr, stage);
     if (OCC) {
         __syncthreads();
-        occ_from_lds<D, LAY>(tab, sd.occ + (int64_t)f * sd.words, 1, tid, BLOCK, sd.tspans == 1);
+        occ_from_lds<D, LAY>(tab, cs.occ + (int64_t)f * cs.words, 1, tid, BLOCK, cs.single != 0);
     }
 }
 
 // The items [i0, i1) (every istep-th) of one launch, the item code of every
-// depth reached through `body`.
+// depth reached through `body` (with the stream's depth).
 template <int MODE, typename Body>
 __device__ __forceinline__ void walk_items(const BatchArgs &b, Body body) {
     const int64_t n_items = *b.n_items;
@@ -155,24 +189,29 @@ __device__ __forceinline__ void walk_items(const BatchArgs &b, Body body) {
         i1 = n_items * (blockIdx.x + 1) / gridDim.x;
         istep = 1;
     }
-    int cur = -1;
+    ItemStream cs{};
+    const BatchStreamDev *slot = nullptr;
     for (int64_t it = i0; it < i1; it += istep) {
-        const int s = stream_of<MODE>(b, it, cur);
-        const BatchStreamDev &sd = b.streams[s];
-        const int64_t local = it - ((MODE & MODE_MASK) ? sd.citem0 : sd.titem0);
-        body(sd, local, s != cur);
-        cur = s;
+        bool fresh = false;
+        if (!slot || it < cs.first || it >= cs.first + cs.count) {
+            slot = &b.streams[stream_of<MODE>(b, it)];
+            cs = load_stream<MODE>(*slot);
+            fresh = true;
+        }
+        body(cs, *slot, it - cs.first, fresh);
     }
 }
 
 // One call per (depth, order) in the one-launch kernel: each depth's code
 // gets its own register allocation (all six inlined take 187 VGPRs, two
 // waves per SIMD); the price is a call per item that saves 12 VGPRs to the
-// stack.
+// stack.  The callee reads the stream's fields from its slot (a copy passed
+// to a call would live on the stack).
 template <int D, int LAY, int MODE, int BLOCK>
 __device__ __attribute__((noinline)) void batch_item(const BatchArgs &b, const BatchStreamDev &sd, int64_t local,
                                                      uint32_t *tab, uint16_t *st_mask, bool new_stream) {
-    item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, new_stream);
+    const ItemStream cs = load_stream<MODE>(sd);
+    item_body<D, LAY, MODE, BLOCK>(b, cs, local, tab, st_mask, new_stream);
 }
 
 // The streams of one depth (b.streams points at the first of them, items
@@ -183,8 +222,8 @@ __global__ __launch_bounds__(BLOCK) void batch_depth_kernel(BatchArgs b) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     __shared__ uint32_t tab[lds_words(D, LAY)];
     __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
-    walk_items<MODE>(b, [&](const BatchStreamDev &sd, int64_t local, bool fresh) {
-        item_body<D, LAY, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh);
+    walk_items<MODE>(b, [&](const ItemStream &cs, const BatchStreamDev &, int64_t local, bool fresh) {
+        item_body<D, LAY, MODE, BLOCK>(b, cs, local, tab, st_mask, fresh);
     });
 }
 
@@ -193,7 +232,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs b) {
     constexpr bool MASK = (MODE & MODE_MASK) != 0;
     __shared__ uint32_t tab[kBatchTableWords];
     __shared__ uint16_t st_mask[MASK ? kStageGroups : 4];
-    walk_items<MODE>(b, [&](const BatchStreamDev &sd, int64_t local, bool fresh) {
+    walk_items<MODE>(b, [&](const ItemStream &, const BatchStreamDev &sd, int64_t local, bool fresh) {
         switch (sd.depth) {
             case 1: batch_item<1, LAY_WIDE, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh); break;
             case 2: batch_item<2, LAY_WIDE, MODE, BLOCK>(b, sd, local, tab, st_mask, fresh); break;
@@ -470,6 +509,8 @@ void split_items(obg_plan *p) {
             int64_t cs = (std::min<int64_t>(p->shape.classify_span, h.groups) + 3) & ~int64_t(3);
             h.cspans = (int32_t)((h.groups + cs - 1) / cs);
             h.cspan = (int32_t)((((h.groups + h.cspans - 1) / h.cspans) + 3) & ~3);
+            h.div_tspans = make_fastdiv((uint32_t)h.tspans);
+            h.div_cspans = make_fastdiv((uint32_t)h.cspans);
             gr.max_train_items += (int64_t)h.tspans * h.max_train;
             gr.max_classify_items += (int64_t)h.cspans * h.max_test;
         }
@@ -797,8 +838,10 @@ int describe(const obg_plan_stream *streams, int32_t n_streams, obg_plan *p) {
     return OBG_OK;
 }
 
-// The launch shape a plan starts from.
-Shape default_shape() { return Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 1) == 2 ? 1 : 0}; }
+// The launch shape a plan starts from: one launch per depth present and
+// phase (faster than one launch per phase on one 1080p stream and on the
+// 64-stream mix).
+Shape default_shape() { return Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 2) == 2 ? 1 : 0}; }
 
 // Device address of `scratch` on each device, looked up once per device with
 // that device current.
