@@ -244,14 +244,15 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(BatchArgs b) {
     });
 }
 
-// Merge of every stream that trained in this run: block row y = slot, one
-// thread per 32 keys.
-__global__ __launch_bounds__(256) void batch_merge_kernel(const BatchStreamDev *streams) {
+// Merge of every stream that trained in this run: block row y = slot, 64
+// words (2048 keys) to a workgroup.
+__global__ __launch_bounds__(kMergeBlock) void batch_merge_kernel(const BatchStreamDev *streams) {
+    __shared__ uint32_t part[(kMergeWaves - 1) * 16 * 64];
     const BatchStreamDev &sd = streams[blockIdx.y];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (sd.n_train < 1 || i >= sd.words) return;
-    sd.leaf[i] = merge_word(sd.occ, sd.n_train, 0, sd.n_train, sd.words, i, sd.valid_bits, sd.kmin,
-                            sd.planes, sd.empty);
+    const int64_t w0 = blockIdx.x * (int64_t)64;
+    if (sd.n_train < 1 || w0 >= sd.words) return;
+    merge_block(sd.occ, sd.n_train, 0, sd.n_train, sd.words, sd.words, w0, sd.valid_bits, sd.kmin, sd.planes,
+                sd.empty, 1, sd.leaf, part);
 }
 
 // Zero the trees of training frames cut into several items (block row y =
@@ -580,7 +581,7 @@ hipError_t enqueue_steps(obg_plan *p, hipStream_t st) {
     if (e != hipSuccess) return e;
     if (p->shape.per_depth) {
         if ((e = enqueue_depths(p, true, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(batch_merge_kernel, dim3((p->max_words + 255) / 256, ny), dim3(256), 0, st,
+        hipLaunchKernelGGL(batch_merge_kernel, dim3((p->max_words + 63) / 64, ny), dim3(kMergeBlock), 0, st,
                            (const BatchStreamDev *)p->d);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         return enqueue_depths(p, false, st);
@@ -594,7 +595,7 @@ hipError_t enqueue_steps(obg_plan *p, hipStream_t st) {
             hipLaunchKernelGGL((batch_kernel<MODE_OCC, 256>), dim3(grid), dim3(256), 0, st, a);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(batch_merge_kernel, dim3((p->max_words + 255) / 256, ny), dim3(256), 0, st,
+    hipLaunchKernelGGL(batch_merge_kernel, dim3((p->max_words + 63) / 64, ny), dim3(kMergeBlock), 0, st,
                        (const BatchStreamDev *)p->d);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (p->max_classify_items > 0) {

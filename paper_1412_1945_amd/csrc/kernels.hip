@@ -18,7 +18,8 @@
 //               not a multiple of 16 pixels; bitsets stay in HBM/L2.
 // merge_kernel  per 32 keys: bit-sliced counters of the window's bitsets and
 //               a bit-sliced compare against the frame-count threshold
-//               (Algorithm 2 in closed form).
+//               (Algorithm 2 in closed form); 64 words to a workgroup, its
+//               four waves count a quarter of the window each.
 #include <algorithm>
 
 #include "strip_core.h"
@@ -277,11 +278,10 @@ __global__ __launch_bounds__(256) void generic_kernel(GenericArgs a, int mode) {
 // ---------------------------------------------------------------------------
 // Merge: bit-sliced frame counts, one thread per 32 keys.
 
-__global__ __launch_bounds__(256) void merge_kernel(MergeArgs a) {
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= a.slot_words) return;
-    a.leaf[i] = merge_word(a.occ_ring, a.ring_len, a.first, a.n_trees, a.slot_words, i,
-                           a.valid_bits_last, a.kmin, a.planes, a.empty, a.group);
+__global__ __launch_bounds__(kMergeBlock) void merge_kernel(MergeArgs a) {
+    __shared__ uint32_t part[(kMergeWaves - 1) * 16 * 64];
+    merge_block(a.occ_ring, a.ring_len, a.first, a.n_trees, a.slot_words, a.slot_words, blockIdx.x * (int64_t)64,
+                a.valid_bits_last, a.kmin, a.planes, a.empty, a.group, a.leaf, part);
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -420,9 +420,8 @@ hipError_t launch_merge(const MergeArgs &a, hipStream_t stream) {
         a.n_trees < 1 || a.n_trees > a.ring_len)
         return hipErrorInvalidValue;
     if (a.slot_words == 0) return hipSuccess;
-    const int block = 256;
-    const int64_t grid = (a.slot_words + block - 1) / block;
-    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)grid), dim3(block), 0, stream, a);
+    const int64_t grid = (a.slot_words + 63) / 64;
+    hipLaunchKernelGGL(merge_kernel, dim3((unsigned)grid), dim3(kMergeBlock), 0, stream, a);
     return hipGetLastError();
 }
 

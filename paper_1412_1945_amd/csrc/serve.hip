@@ -43,17 +43,19 @@ struct ServeFrameDev {
     uint64_t *mask;           // test frames; NULL for training frames
     int32_t depth, groups, words;
     int32_t native;           // ring slot and leaf set in the LDS order (d = 5, 6)
+    int32_t whole;            // one workgroup takes the whole frame: its tree is stored, not ORed
     int64_t g0;               // first group of the frame in the batch's group space
 };
 
 // A batch is one space of 16-pixel groups: its frames' groups end to end.
-// Workgroup w takes groups [w*chunk, (w+1)*chunk), whatever frames they fall
-// in, so every workgroup has the same number of pixels to read.
+// Workgroup w takes groups [bounds[w], bounds[w+1]), whatever frames they
+// fall in; the runs are cut so that they cost about the same (split_by_cost),
+// and a cut inside a frame is a multiple of 4 groups from its start, so mask
+// words never straddle workgroups.
 struct ServeArgs {
     const ServeFrameDev *frames;
     int32_t n_frames;
-    int64_t n_groups;
-    int64_t chunk;            // multiple of 4: mask words never straddle workgroups
+    const int64_t *bounds;    // [grid + 1]
 };
 
 struct MergeJobDev {
@@ -81,9 +83,10 @@ __device__ __forceinline__ int frame_of(const ServeArgs &b, int64_t g) {
 }
 
 // Groups [gb, ge) of one frame: its occupancy is built in LDS and ORed into the
-// frame's ring slot; test frames also get their mask bits from the leaf set,
-// in one dual table (leaf and occupancy words in pairs), training frames use
-// an occupancy table in the same memory.
+// frame's ring slot (stored, when this is the whole frame); test frames also
+// get their mask bits from the leaf set, in one dual table (leaf and
+// occupancy words in pairs), training frames use an occupancy table in the
+// same memory.
 template <int D, int LAY, int MODE>
 __device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, int gb, int ge, uint32_t *tab,
                                                      uint16_t *stage, bool load_leaf) {
@@ -115,7 +118,7 @@ __device__ __attribute__((noinline)) void serve_part(const ServeFrameDev &fd, in
         span_loop<D, MODE, LAY, false, kServeBlock>(a, rs, ms, gb, ge, tab, tab, nullptr, nullptr);
     }
     __syncthreads();
-    occ_from_lds<D, LAY, MASK>(tab, fd.occ, 1, tid, kServeBlock, false, fd.native != 0);
+    occ_from_lds<D, LAY, MASK>(tab, fd.occ, 1, tid, kServeBlock, fd.whole != 0, fd.native != 0);
 }
 
 template <int MODE>
@@ -136,8 +139,8 @@ __device__ __forceinline__ void serve_dispatch(const ServeFrameDev &fd, int gb, 
 __global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))) void serve_kernel(ServeArgs b) {
     __shared__ uint32_t tab[2 * kServeTableWords];
     __shared__ uint16_t stage[kMaxStageGroups];
-    int64_t g = (int64_t)blockIdx.x * b.chunk;
-    const int64_t gend = min(g + b.chunk, b.n_groups);
+    int64_t g = b.bounds[blockIdx.x];
+    const int64_t gend = b.bounds[blockIdx.x + 1];
     if (g >= gend) return;
     int fi = frame_of(b, g);
     const uint32_t *cur_leaf = nullptr;
@@ -157,18 +160,23 @@ __global__ __launch_bounds__(kServeBlock) __attribute__((amdgpu_waves_per_eu(4))
     }
 }
 
-// Zero the ring slots that this batch's frames OR their occupancy into.
+// Zero the ring slots that this batch's frames OR their occupancy into (the
+// frames that several workgroups share).
 __global__ __launch_bounds__(256) void serve_zero_kernel(const ServeFrameDev *frames) {
     const ServeFrameDev &fd = frames[blockIdx.y];
+    if (fd.whole) return;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < fd.words; i += gridDim.x * blockDim.x) fd.occ[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void serve_merge_kernel(const MergeJobDev *jobs) {
+// The batch's due merges: block row y = job, 64 words (2048 keys) to a
+// workgroup.
+__global__ __launch_bounds__(kMergeBlock) void serve_merge_kernel(const MergeJobDev *jobs) {
+    __shared__ uint32_t part[(kMergeWaves - 1) * 16 * 64];
     const MergeJobDev &j = jobs[blockIdx.y];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= j.words) return;
-    j.leaf[i] = merge_word(j.ring, j.ring_len, j.first, j.n_trees, j.words, i, j.valid_bits, j.kmin, j.planes,
-                           j.empty);
+    const int64_t w0 = blockIdx.x * (int64_t)64;
+    if (w0 >= j.words) return;
+    merge_block(j.ring, j.ring_len, j.first, j.n_trees, j.words, j.words, w0, j.valid_bits, j.kmin, j.planes,
+                j.empty, 1, j.leaf, part);
 }
 
 // Per test frame: an order-dependent 64-bit hash of its mask words.
@@ -215,6 +223,7 @@ struct Slot {
     std::vector<int> order;        // launch order of the batch's frames (indices into batch.frames)
     int n_train_plain = 0;         // order: plain training, plain test, region test, region training
     ServeFrameDev *h_frames = nullptr, *d_frames = nullptr;
+    int64_t *h_bounds = nullptr, *d_bounds = nullptr;   // serve_kernel's runs (grid + 1)
     MergeJobDev *h_jobs = nullptr, *d_jobs = nullptr;
     // frame lists of the region frames: pixels, masks, ring slots (maxf each)
     void **h_lists = nullptr, **d_lists = nullptr;
@@ -223,6 +232,20 @@ struct Slot {
 };
 
 int sfail(int code, const char *msg) { return set_error(code, msg); }
+
+// Relative cost of one 16-pixel group in serve_kernel, by depth and by kind
+// (training frames build a tree, test frames also classify), and of one
+// piece of a frame taken by a workgroup (leaf set into LDS, tree out, the
+// pipeline refilled).  Fitted to per-workgroup times over the mixed served
+// workload on MI355X: 65 units are about 5.2 ns of one workgroup at two
+// workgroups per CU; a piece costs about 8 us, some 1500 groups.
+int32_t serve_group_cost(int depth, bool test) {
+    static const int32_t train[9] = {65, 65, 65, 65, 65, 68, 67, 67, 67};
+    static const int32_t test_[9] = {66, 66, 66, 66, 69, 70, 74, 74, 74};
+    const int d = depth < 0 ? 0 : (depth > 8 ? 8 : depth);
+    return test ? test_[d] : train[d];
+}
+constexpr int64_t kServePartCost = 98000;
 
 // total length covered by a set of [begin, end] intervals
 double union_length(std::vector<std::pair<double, double>> iv) {
@@ -459,6 +482,15 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
         }
     }
     const int maxf = cfg->max_batch_frames;
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) cus = n;
+    }
+    const int max_grid = 2 * cus;   // serve_kernel: two resident workgroups per CU
+    std::vector<int64_t> cut_groups(maxf);
+    std::vector<int32_t> cut_weight(maxf);
+    std::vector<uint8_t> cut_whole(maxf);
     std::vector<Slot> slots(cfg->max_inflight);
     for (auto &sl : slots) {
         if (rc != OBG_OK) break;
@@ -467,6 +499,8 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             hipEventCreate(&sl.k0) != hipSuccess || hipEventCreate(&sl.k1) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_frames, sizeof(ServeFrameDev) * maxf, hipHostMallocDefault) != hipSuccess ||
             hipMalloc((void **)&sl.d_frames, sizeof(ServeFrameDev) * maxf) != hipSuccess ||
+            hipHostMalloc((void **)&sl.h_bounds, sizeof(int64_t) * (max_grid + 1), hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void **)&sl.d_bounds, sizeof(int64_t) * (max_grid + 1)) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_jobs, sizeof(MergeJobDev) * ns, hipHostMallocDefault) != hipSuccess ||
             hipMalloc((void **)&sl.d_jobs, sizeof(MergeJobDev) * ns) != hipSuccess ||
             hipHostMalloc((void **)&sl.h_sum, sizeof(unsigned long long) * maxf, hipHostMallocDefault) != hipSuccess ||
@@ -480,11 +514,6 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
     }
     hipEvent_t t0 = nullptr;
     if (rc == OBG_OK && hipEventCreate(&t0) != hipSuccess) rc = sfail(OBG_EHIP, "event");
-    int cus = 256, dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int n = 0;
-        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) cus = n;
-    }
     std::vector<double> lat;
     lat.reserve(arr.size());
     std::vector<std::pair<double, double>> busy_iv, path_iv;   // per batch, ms after t0
@@ -606,6 +635,20 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                     sl.h_lists[2 * maxf + p - n_plain] = fd.occ;
                 }
             }
+            // serve_kernel's runs, cut by cost; at least kMinChunk groups per
+            // workgroup, so that a small batch does not pay for idle ones
+            int grid = 0;
+            if (n_plain) {
+                const int64_t kMinChunk = 2048;
+                grid = (int)std::max<int64_t>(1, std::min<int64_t>((n_groups + kMinChunk - 1) / kMinChunk, max_grid));
+                for (int p = 0; p < n_plain; ++p) {
+                    cut_groups[p] = sl.h_frames[p].groups;
+                    cut_weight[p] = serve_group_cost(sl.h_frames[p].depth, sl.h_frames[p].mask != nullptr);
+                }
+                split_by_cost(cut_groups.data(), cut_weight.data(), n_plain, kServePartCost, grid, sl.h_bounds,
+                              cut_whole.data());
+            }
+            for (int p = 0; p < n; ++p) sl.h_frames[p].whole = p < n_plain ? cut_whole[p] : 0;
             // merges of plain streams in one launch; region streams merge alone
             int n_jobs = 0;
             for (const SchedMerge &m : sl.batch.merges)
@@ -616,6 +659,9 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             hipStream_t st = sl.st;
             bool ok = hipEventRecord(sl.start, st) == hipSuccess;
             if (ok) ok = hipMemcpyAsync(sl.d_frames, sl.h_frames, sizeof(ServeFrameDev) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+            if (ok && grid)
+                ok = hipMemcpyAsync(sl.d_bounds, sl.h_bounds, sizeof(int64_t) * (grid + 1), hipMemcpyHostToDevice, st) ==
+                     hipSuccess;
             if (ok && n_jobs)
                 ok = hipMemcpyAsync(sl.d_jobs, sl.h_jobs, sizeof(MergeJobDev) * n_jobs, hipMemcpyHostToDevice, st) == hipSuccess;
             if (ok && n > n_plain)
@@ -627,14 +673,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 if (n_plain) {
                     hipLaunchKernelGGL(serve_zero_kernel, dim3(8, n_plain), dim3(256), 0, st,
                                        (const ServeFrameDev *)sl.d_frames);
-                    // equal runs of groups, at least kMinChunk per workgroup so
-                    // that a small batch does not pay for idle workgroups
-                    const int64_t kMinChunk = 2048;
-                    int64_t grid = std::min<int64_t>((n_groups + kMinChunk - 1) / kMinChunk, (int64_t)cus * 2);
-                    grid = std::max<int64_t>(grid, 1);
-                    const int64_t chunk = (((n_groups + grid - 1) / grid) + 3) & ~int64_t(3);
-                    grid = (n_groups + chunk - 1) / chunk;
-                    ServeArgs b{sl.d_frames, n_plain, n_groups, chunk};
+                    ServeArgs b{sl.d_frames, n_plain, sl.d_bounds};
                     hipLaunchKernelGGL(serve_kernel, dim3((unsigned)grid), dim3(kServeBlock), 0, st, b);
                 }
                 // frames with regions: one pass per run of a stream's test
@@ -668,7 +707,7 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
                 if (ok && n_jobs) {
                     int maxw = 1;
                     for (int i = 0; i < n_jobs; ++i) maxw = std::max(maxw, sl.h_jobs[i].words);
-                    hipLaunchKernelGGL(serve_merge_kernel, dim3((maxw + 255) / 256, n_jobs), dim3(256), 0, st,
+                    hipLaunchKernelGGL(serve_merge_kernel, dim3((maxw + 63) / 64, n_jobs), dim3(kMergeBlock), 0, st,
                                        (const MergeJobDev *)sl.d_jobs);
                 }
                 for (const SchedMerge &m : sl.batch.merges) {
@@ -787,6 +826,8 @@ extern "C" int obg_serve_run(const obg_serve_config *cfg, obg_serve_stats *stats
             if (ev) (void)hipEventDestroy(ev);
         if (sl.h_frames) (void)hipHostFree(sl.h_frames);
         if (sl.d_frames) (void)hipFree(sl.d_frames);
+        if (sl.h_bounds) (void)hipHostFree(sl.h_bounds);
+        if (sl.d_bounds) (void)hipFree(sl.d_bounds);
         if (sl.h_jobs) (void)hipHostFree(sl.h_jobs);
         if (sl.d_jobs) (void)hipFree(sl.d_jobs);
         if (sl.h_sum) (void)hipHostFree(sl.h_sum);

@@ -23,6 +23,7 @@
 //     nothing else is admitted until it fits (no stream starves).
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
 #include <deque>
 #include <set>
@@ -221,5 +222,48 @@ class ServeScheduler {
         return block_bytes(ws, ws.queued.front() >= ws.cfg.n_train) > arena.largest();
     }
 };
+
+// Runs of 16-pixel groups for the `grid` workgroups of one pass over the
+// frames of a batch, laid end to end.  Frame f has groups[f] groups (a
+// multiple of 4) and costs weight[f] per group, plus part_cost for every
+// workgroup that takes a piece of it (loading its leaf set, flushing its
+// tree, refilling the pipeline).  Workgroup w takes groups
+// [bounds[w], bounds[w+1]) (bounds has grid + 1 entries); the runs cost about
+// total / grid each.  A run boundary inside a frame is a multiple of 4 groups
+// from the frame's start (whole 64-pixel mask words); one that would leave
+// less than half a part's worth of groups on either side moves to the
+// frame's edge.  whole[f] = 1 when a single workgroup takes all of frame f.
+inline void split_by_cost(const int64_t *groups, const int32_t *weight, int n, int64_t part_cost, int grid,
+                          int64_t *bounds, uint8_t *whole) {
+    std::vector<double> c0(n + 1, 0.0);
+    std::vector<int64_t> g0(n + 1, 0);
+    for (int f = 0; f < n; ++f) {
+        c0[f + 1] = c0[f] + (double)part_cost + (double)groups[f] * weight[f];
+        g0[f + 1] = g0[f] + groups[f];
+    }
+    bounds[0] = 0;
+    bounds[grid] = g0[n];
+    int f = 0;
+    for (int w = 1; w < grid; ++w) {
+        const double t = c0[n] * w / grid;
+        while (f < n - 1 && c0[f + 1] <= t) ++f;
+        int64_t off = 0;
+        if (n > 0) {
+            const double into = (t - c0[f] - (double)part_cost) / weight[f];
+            off = into <= 0 ? 0 : std::min<int64_t>(groups[f], (int64_t)into) & ~int64_t(3);
+            const int64_t snap = part_cost / (2 * (int64_t)weight[f]);
+            if (off < snap)
+                off = 0;
+            else if (groups[f] - off < snap)
+                off = groups[f];
+        }
+        bounds[w] = std::max(bounds[w - 1], g0[f] + off);
+    }
+    int w = 1;
+    for (int q = 0; q < n; ++q) {
+        while (w < grid && bounds[w] <= g0[q]) ++w;
+        whole[q] = (w >= grid || bounds[w] >= g0[q + 1]) ? 1 : 0;
+    }
+}
 
 }  // namespace obg

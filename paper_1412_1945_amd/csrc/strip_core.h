@@ -334,65 +334,52 @@ __device__ __forceinline__ void span_loop(const StripArgs &a, __amdgpu_buffer_rs
     }
 }
 
-// One merged word (32 keys) of Algorithm 2 in closed form: bit-sliced
-// counters of the window's bitsets, then a bit-sliced compare with kmin.  With
-// group > 1 the window's trees are taken in groups of `group` consecutive
-// slots (the last may be shorter) and each group counts once, as the OR of its
-// trees (the tree of a group of frames, Section 3); n_trees is the window
-// length in slots.
-__device__ __forceinline__ uint32_t merge_word(const uint32_t *__restrict__ ring, int ring_len, int first,
-                                               int n_trees, int64_t slot_words, int64_t i, int valid_bits,
-                                               uint32_t kmin, int planes, int empty, int group = 1) {
-    const uint32_t valid = valid_bits >= 32 ? 0xFFFFFFFFu : ((1u << valid_bits) - 1u);
-    if (empty) return 0;
-    uint32_t c[16];
-#pragma unroll
-    for (int b = 0; b < 16; ++b) c[b] = 0;
+// Algorithm 2 in closed form, 32 keys to a word: per key, the number of the
+// window's trees that hold it, in bit-sliced counters (plane b holds bit b of
+// the 32 counts), compared bit-sliced with kmin.  With group > 1 the window's
+// trees are taken in groups of `group` consecutive slots (the last may be
+// shorter) and each group counts once, as the OR of its trees (the tree of a
+// group of frames, Section 3); n_trees is the window length in slots.
+constexpr int kMergeWaves = 4;      // waves of a merge workgroup: 64 words x 4 parts of the window
+constexpr int kMergeBlock = 64 * kMergeWaves;
+
+// Add into c the trees (or groups) j = j0, j0 + step, ... of the window for
+// word i.  Sixteen loads per round, independent and in flight together.
+__device__ __forceinline__ void merge_count(uint32_t (&c)[16], const uint32_t *__restrict__ ring, int ring_len,
+                                            int first, int n_trees, int64_t slot_words, int64_t i, uint32_t valid,
+                                            int planes, int group, int j0, int step) {
     const int n_groups = (n_trees + group - 1) / group;
-    if (group == 1) {
-        // one tree per slot: sixteen loads per round, independent and in
-        // flight together (a merge is a few dependent rounds of HBM latency)
-        for (int j0 = 0; j0 < n_trees; j0 += 16) {
-            uint32_t x[16];
+    for (int j = j0; j < n_groups; j += 16 * step) {
+        uint32_t x[16];
+        if (group == 1) {
+            // straight-line loads: none waits for another
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                int sl = first + j0 + k;
+                const int t = j + k * step;
+                int sl = first + t;
                 if (sl >= ring_len) sl -= ring_len;
-                x[k] = (j0 + k < n_trees) ? (ring[(int64_t)sl * slot_words + i] & valid) : 0u;
+                x[k] = t < n_trees ? ring[(int64_t)sl * slot_words + i] : 0u;
             }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) x[k] &= valid;
+        } else {
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                uint32_t carry = x[k];
-#pragma unroll
-                for (int b = 0; b < 16; ++b) {
-                    if (b < planes) {
-                        const uint32_t tmp = c[b] & carry;
-                        c[b] ^= carry;
-                        carry = tmp;
+                x[k] = 0;
+                const int jj = j + k * step;
+                if (jj < n_groups) {
+                    const int tb = jj * group, te = min(tb + group, n_trees);
+                    for (int t = tb; t < te; ++t) {
+                        int sl = first + t;
+                        if (sl >= ring_len) sl -= ring_len;
+                        x[k] |= ring[(int64_t)sl * slot_words + i];
                     }
+                    x[k] &= valid;
                 }
             }
         }
-    }
-    // groups of frames: eight groups per round, their loads in flight together
-    for (int j0 = 0; group > 1 && j0 < n_groups; j0 += 8) {
-        uint32_t x[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            x[k] = 0;
-            if (j0 + k < n_groups) {
-                const int tb = (j0 + k) * group;
-                const int te = min(tb + group, n_trees);
-                for (int t = tb; t < te; ++t) {
-                    int sl = first + t;
-                    if (sl >= ring_len) sl -= ring_len;
-                    x[k] |= ring[(int64_t)sl * slot_words + i];
-                }
-                x[k] &= valid;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < 16; ++k) {
             uint32_t carry = x[k];
 #pragma unroll
             for (int b = 0; b < 16; ++b) {
@@ -401,6 +388,49 @@ __device__ __forceinline__ uint32_t merge_word(const uint32_t *__restrict__ ring
                     c[b] ^= carry;
                     carry = tmp;
                 }
+            }
+        }
+    }
+}
+
+// Words w0 .. w0+63 of one merge by a workgroup of kMergeBlock threads (the
+// call is workgroup-uniform): wave q counts the window's trees j = q, q + 4,
+// ... for the 64 words, the four partial counts meet in LDS (`part`, 3 x 16 x
+// 64 words) and the first wave adds them bit-sliced, compares with kmin and
+// writes leaf[w0 .. w0+63] (words below `words` only).
+__device__ __forceinline__ void merge_block(const uint32_t *__restrict__ ring, int ring_len, int first, int n_trees,
+                                            int64_t slot_words, int64_t words, int64_t w0, int valid_bits,
+                                            uint32_t kmin, int planes, int empty, int group,
+                                            uint32_t *__restrict__ leaf, uint32_t *part) {
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t i = w0 + lane;
+    const uint32_t valid = valid_bits >= 32 ? 0xFFFFFFFFu : ((1u << valid_bits) - 1u);
+    if (empty) {
+        if (q == 0 && i < words) leaf[i] = 0;
+        return;
+    }
+    uint32_t c[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b) c[b] = 0;
+    if (i < words) merge_count(c, ring, ring_len, first, n_trees, slot_words, i, valid, planes, group, q, kMergeWaves);
+    if (q > 0) {
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+            if (b < planes) part[((q - 1) * 16 + b) * 64 + lane] = c[b];
+    }
+    __syncthreads();
+    if (q != 0) return;
+#pragma unroll
+    for (int r = 0; r < kMergeWaves - 1; ++r) {
+        // c += part r, bit-sliced ripple carry (the sum of all counts fits in
+        // `planes` bits: it is at most n_trees)
+        uint32_t carry = 0;
+#pragma unroll
+        for (int b = 0; b < 16; ++b) {
+            if (b < planes) {
+                const uint32_t x = part[(r * 16 + b) * 64 + lane], y = c[b];
+                c[b] = x ^ y ^ carry;
+                carry = (x & y) | (carry & (x ^ y));
             }
         }
     }
@@ -415,7 +445,7 @@ __device__ __forceinline__ uint32_t merge_word(const uint32_t *__restrict__ ring
         }
     }
     ge |= eq;
-    return ge & valid;
+    if (i < words) leaf[i] = ge & valid;
 }
 
 }  // namespace obg

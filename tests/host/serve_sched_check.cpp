@@ -66,6 +66,55 @@ static bool conflict(const std::vector<Access> &a, const std::vector<Access> &b)
     return false;
 }
 
+// split_by_cost: the runs of serve_kernel's workgroups cover the group space
+// in order, cut inside frames only at multiples of 4 groups, flag exactly the
+// frames that one run holds whole, and cost at most total / grid plus the
+// pieces' overhead and the snapping slack each.
+static void check_split() {
+    int trial = 0;
+    for (trial = 0; trial < 4000; ++trial) {
+        const int n = rint(1, 300);
+        const int grid = rint(1, 600);
+        const int64_t part = rint(0, 3) == 0 ? 0 : (int64_t)rint(1, 200000);
+        std::vector<int64_t> groups(n), g0(n + 1, 0);
+        std::vector<int32_t> weight(n);
+        for (int f = 0; f < n; ++f) {
+            const int kind = rint(0, 3);
+            groups[f] = 4 * (int64_t)(kind == 0 ? rint(1, 8) : kind == 1 ? rint(1, 2000) : rint(1, 150000));
+            weight[f] = rint(60, 80);
+            g0[f + 1] = g0[f] + groups[f];
+        }
+        std::vector<int64_t> b(grid + 1, -1);
+        std::vector<uint8_t> whole(n, 7);
+        split_by_cost(groups.data(), weight.data(), n, part, grid, b.data(), whole.data());
+        CHECK(b[0] == 0 && b[grid] == g0[n]);
+        double total = 0;
+        int32_t wmax = 0;
+        for (int f = 0; f < n; ++f) {
+            total += (double)part + (double)groups[f] * weight[f];
+            wmax = std::max(wmax, weight[f]);
+        }
+        for (int w = 0; w < grid; ++w) {
+            CHECK(b[w] <= b[w + 1]);
+            // a cut inside frame f is 4-aligned from its start
+            const int f = (int)(std::upper_bound(g0.begin(), g0.end(), b[w]) - g0.begin()) - 1;
+            if (f >= 0 && f < n) CHECK((b[w] - g0[f]) % 4 == 0);
+            // cost of the run: groups by weight, one piece overhead per frame touched
+            double c = 0;
+            for (int q = 0; q < n; ++q) {
+                const int64_t lo = std::max(b[w], g0[q]), hi = std::min(b[w + 1], g0[q + 1]);
+                if (hi > lo) c += (double)part + (double)(hi - lo) * weight[q];
+            }
+            CHECK(c <= total / grid + 2.0 * (double)part + 8.0 * wmax + 1.0);
+        }
+        for (int f = 0; f < n; ++f) {
+            bool cut = false;
+            for (int w = 1; w < grid; ++w) cut = cut || (b[w] > g0[f] && b[w] < g0[f + 1]);
+            CHECK(whole[f] == (cut ? 0 : 1));
+        }
+    }
+}
+
 int main() {
     int trial = 0, hopeless_runs = 0, waits_runs = 0, batches_total = 0;
     for (trial = 0; trial < 3000; ++trial) {
@@ -204,6 +253,7 @@ int main() {
     trial = -1;
     CHECK(hopeless_runs > 0);
     CHECK(waits_runs > 100);
+    check_split();
     if (fails) {
         printf("%d checks failed\n", fails);
         return 1;
