@@ -36,6 +36,9 @@ def parse():
                    choices=["plain1080", "region4k", "small", "batched", "served"])
     p.add_argument("--streams", type=int, default=64, help="streams of the batched workload")
     p.add_argument("--n-test", type=int, default=None, help="override the number of test frames")
+    p.add_argument("--depth", type=int, default=None, choices=range(1, 9), metavar="1..8",
+                   help="one-stream workloads: override the tree depth (the timed step and the roofline line "
+                        "then describe that depth)")
     p.add_argument("--serve-seconds", type=float, default=60.0,
                    help="simulated seconds of arrivals in the real-time served run")
     p.add_argument("--serve-capacity-seconds", type=float, default=10.0,
@@ -225,13 +228,20 @@ def knob_sweep(reps=5):
     print(json.dumps({"knob_sweep": rows}), flush=True)
 
 
-def workload(name, n_test):
+def workload(name, n_test, depth=None):
+    """The one-stream workload; `depth` replaces its tree depth (and the
+    depth in its name)."""
+    from dataclasses import replace
     from synth import frames as S
     if name == "plain1080":
-        return S.cfg1(n_test=n_test or 1000)
-    if name == "region4k":
-        return S.cfg2(n_test=n_test or 500)
-    return S.cfg0()
+        wl = S.cfg1(n_test=n_test or 1000)
+    elif name == "region4k":
+        wl = S.cfg2(n_test=n_test or 500)
+    else:
+        wl = S.cfg0()
+    if depth is None or depth == wl.depth[0]:
+        return wl
+    return replace(wl, name=wl.name.replace(f"-d{wl.depth[0]}", f"-d{depth}"), depth=[depth] * len(wl.streams))
 
 
 def host_cpu():
@@ -714,7 +724,7 @@ def main():
 
     obg.load()
     dev = torch.device("cuda:0")
-    wl = workload(a.workload, a.n_test)
+    wl = workload(a.workload, a.n_test, a.depth)
     spec = wl.streams[0]
     depth = wl.depth[0]
     num, den = wl.thr[0]
