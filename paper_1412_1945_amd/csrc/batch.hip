@@ -491,16 +491,26 @@ namespace {
 // Split every stream's frames into work items for the current shape (host
 // copies of the slots only).
 void split_items(obg_plan *p) {
-    int64_t tgroups = 0;
-    for (const auto &h : p->h) tgroups += (int64_t)h.groups * h.max_train;
+    int64_t all_groups = 0;
+    for (const auto &h : p->h) all_groups += (int64_t)h.groups * h.max_train;
     const int64_t train_wgs = (int64_t)p->cus * p->shape.train_wpc;
-    // training items: about train_items_per_wg per workgroup when every
-    // stream trains on its most frames, whole frames when they are small
-    // enough (one LDS flush per item)
-    int64_t tspan_target = tgroups / std::max<int64_t>(1, train_wgs * p->shape.train_items_per_wg);
-    tspan_target = std::max<int64_t>(tspan_target, 4096);
     p->max_train_items = p->max_classify_items = 0;
     for (auto &gr : p->groups) {
+        // training items: about train_items_per_wg per workgroup of the
+        // launch that runs them when every stream trains on its most frames
+        // (with one launch per depth, that depth's frames: each launch has
+        // the whole grid), whole frames when they are small enough.  Items
+        // are dealt to workgroups by count, so they should be of about one
+        // size: a frame far larger than the others' items is cut.  At least
+        // 4096 groups, and 4 groups per tree word (each item flushes its
+        // tree once: at most about 2 % of its pixel bytes)
+        int64_t tgroups = all_groups;
+        if (p->shape.per_depth) {
+            tgroups = 0;
+            for (int s = gr.s0; s < gr.s1; ++s) tgroups += (int64_t)p->h[s].groups * p->h[s].max_train;
+        }
+        int64_t tspan_target = tgroups / std::max<int64_t>(1, train_wgs * p->shape.train_items_per_wg);
+        tspan_target = std::max<int64_t>(tspan_target, std::max<int64_t>(4096, 4 * (int64_t)leaf_words(gr.depth)));
         gr.max_train_items = gr.max_classify_items = 0;
         for (int s = gr.s0; s < gr.s1; ++s) {
             BatchStreamDev &h = p->h[s];
@@ -721,7 +731,7 @@ int autotune(obg_plan *p, const obg_work_item *items, int32_t n_items, hipStream
         if ((rc = trial(s))) return rc;
     }
     const int cblocks[] = {256, 512}, cwpcs[] = {1, 2, 4}, cspans[] = {256, 512, 832, 1024, 4096};
-    const int tblocks[] = {256, 1024}, twpcs[] = {1, 2, 4}, titems[] = {1, 4};
+    const int tblocks[] = {256, 1024}, twpcs[] = {1, 2, 4}, titems[] = {1, 4, 16};
     for (int cb : cblocks)
         for (int cw : cwpcs)
             for (int cs : cspans)
@@ -841,8 +851,9 @@ int describe(const obg_plan_stream *streams, int32_t n_streams, obg_plan *p) {
 
 // The launch shape a plan starts from: one launch per depth present and
 // phase (faster than one launch per phase on one 1080p stream and on the
-// 64-stream mix).
-Shape default_shape() { return Shape{256, 4, 4, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 2) == 2 ? 1 : 0}; }
+// 64-stream mix), training items of about a sixteenth of a workgroup's share
+// (the 64-stream mix: 22.1 against 23.3 ms with a quarter).
+Shape default_shape() { return Shape{256, 4, 16, 512, 2, 832, 1, tune(OBG_TUNE_BATCH_PER_DEPTH, 2) == 2 ? 1 : 0}; }
 
 // Device address of `scratch` on each device, looked up once per device with
 // that device current.
