@@ -456,6 +456,16 @@ struct Shape {
     int per_depth;            // 1: one launch per depth and phase, 0: one launch per phase
 };
 
+// Classify items of a stream of depth d: the shape's span, twice that with the
+// compact table of d = 6 (as in one-stream calls; the 64-stream mix, untuned:
+// 22.6-22.8 against 23.0-23.6 ms).  The longest items of a launch decide
+// whether its masks are staged, so the one-launch form asks for the span of
+// the deepest stream.
+constexpr int kCompactDepth = 6;
+inline int64_t classify_span_of(const Shape &sh, int d) {
+    return (d >= kCompactDepth ? 2 : 1) * (int64_t)sh.classify_span;
+}
+
 // Streams of one depth: slots [s0, s1).
 struct DepthGroup {
     int depth, s0, s1;
@@ -517,7 +527,7 @@ void split_items(obg_plan *p) {
             int64_t ts = (std::min<int64_t>(tspan_target, h.groups) + 3) & ~int64_t(3);
             h.tspans = (int32_t)((h.groups + ts - 1) / ts);
             h.tspan = (int32_t)((((h.groups + h.tspans - 1) / h.tspans) + 3) & ~3);
-            int64_t cs = (std::min<int64_t>(p->shape.classify_span, h.groups) + 3) & ~int64_t(3);
+            int64_t cs = (std::min<int64_t>(classify_span_of(p->shape, gr.depth), h.groups) + 3) & ~int64_t(3);
             h.cspans = (int32_t)((h.groups + cs - 1) / cs);
             h.cspan = (int32_t)((((h.groups + h.cspans - 1) / h.cspans) + 3) & ~3);
             h.div_tspans = make_fastdiv((uint32_t)h.tspans);
@@ -553,7 +563,7 @@ hipError_t launch_depth(obg_plan *p, int g, bool train, hipStream_t st) {
         else
             hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_OCC, 256>), dim3(grid), dim3(256), 0, st, a);
     } else {
-        BatchArgs a{d, n, p->d_totals + 2 * g + 1, sh.classify_rr, sh.classify_span <= kStageGroups ? 1 : 0};
+        BatchArgs a{d, n, p->d_totals + 2 * g + 1, sh.classify_rr, classify_span_of(sh, D) <= kStageGroups ? 1 : 0};
         const int grid = (int)std::min<int64_t>(gr.max_classify_items, (int64_t)p->cus * sh.classify_wpc);
         if (sh.classify_block == 512)
             hipLaunchKernelGGL((batch_depth_kernel<D, LAY, MODE_MASK, 512>), dim3(grid), dim3(512), 0, st, a);
@@ -613,8 +623,10 @@ hipError_t enqueue_steps(obg_plan *p, hipStream_t st) {
         // memory, and items are numbered stream by stream, so a workgroup
         // reloads a leaf table only where its items cross into the next
         // stream; contiguous runs meet each stream's table once
+        int deepest = 1;
+        for (const DepthGroup &gr : p->groups) deepest = std::max(deepest, gr.depth);
         BatchArgs a{p->d, ny, p->d_totals + 2 * kDepthGroups + 1, p->shape.classify_rr,
-                    p->shape.classify_span <= kStageGroups ? 1 : 0};
+                    classify_span_of(p->shape, deepest) <= kStageGroups ? 1 : 0};
         const int grid = (int)std::min<int64_t>(p->max_classify_items, (int64_t)p->cus * p->shape.classify_wpc);
         if (p->shape.classify_block == 512)
             hipLaunchKernelGGL((batch_kernel<MODE_MASK, 512>), dim3(grid), dim3(512), 0, st, a);
