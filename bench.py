@@ -453,8 +453,23 @@ def batched_leg(a, steps, warmup, verify_oracle=False):
     ms_plain, host_plain = timed(plain_per_frame, 2)
     same = all(torch.equal(s["occ"], s["p_occ"]) and torch.equal(s["leafset"], s["p_leaf"])
                and torch.equal(s["mask"], s["p_mask"]) for s in streams)
+    def timed_median(fn, reps):
+        # each repetition bracketed by its own events: a host stall between
+        # launches (the per-stream form issues 3 calls per stream from
+        # Python) shows in one repetition, not in the median
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[len(ts) // 2], ts
+
     print("# batched: plain per stream", file=sys.stderr, flush=True)
-    ms_stream, _ = timed(plain_per_stream, 3)
+    ms_stream, stream_reps = timed_median(plain_per_stream, 5)
     same2 = all(torch.equal(s["mask"], s["p_mask"]) and torch.equal(s["leafset"], s["p_leaf"]) for s in streams)
     bytes_step = 3 * px + px_test // 8 + sum(s["n_train"] * s["geom"].words * 4 for s in streams)
     out = {
@@ -465,7 +480,8 @@ def batched_leg(a, steps, warmup, verify_oracle=False):
         "plain_per_frame": {"ms": round(ms_plain, 3), "host_ms": round(host_plain, 3),
                             "gpixel_s": round(px / (ms_plain * 1e-3) / 1e9, 1),
                             "launches": sum(c[9] + c[10] + 1 for c in calls)},
-        "plain_per_stream": {"ms": round(ms_stream, 3), "gpixel_s": round(px / (ms_stream * 1e-3) / 1e9, 1)},
+        "plain_per_stream": {"ms": round(ms_stream, 3), "gpixel_s": round(px / (ms_stream * 1e-3) / 1e9, 1),
+                             "ms_reps": [round(t, 3) for t in stream_reps], "statistic": "median of 5"},
         "batched_vs_plain": round(ms_plain / ms_batched, 2),
         "batched_vs_per_stream": round(ms_stream / ms_batched, 2),
         "bit_exact_vs_plain": bool(same and same2 and status_ok),
