@@ -237,15 +237,16 @@ int sfail(int code, const char *msg) { return set_error(code, msg); }
 // (training frames build a tree, test frames also classify), and of one
 // piece of a frame taken by a workgroup (leaf set into LDS, tree out, the
 // pipeline refilled).  Fitted to per-workgroup times over the mixed served
-// workload on MI355X: 65 units are about 5.2 ns of one workgroup at two
-// workgroups per CU; a piece costs about 8 us, some 1500 groups.
+// workload on MI355X (batches of up to 1024 frames): 63 units are about
+// 5.0 ns of one workgroup at two workgroups per CU; a piece costs about
+// 10 us, some 2000 groups.
 int32_t serve_group_cost(int depth, bool test) {
-    static const int32_t train[9] = {65, 65, 65, 65, 65, 68, 67, 67, 67};
-    static const int32_t test_[9] = {66, 66, 66, 66, 69, 70, 74, 74, 74};
+    static const int32_t train[9] = {63, 63, 63, 63, 64, 63, 63, 63, 63};
+    static const int32_t test_[9] = {65, 65, 65, 65, 66, 66, 71, 71, 71};
     const int d = depth < 0 ? 0 : (depth > 8 ? 8 : depth);
     return test ? test_[d] : train[d];
 }
-constexpr int64_t kServePartCost = 98000;
+constexpr int64_t kServePartCost = 130000;
 
 // total length covered by a set of [begin, end] intervals
 double union_length(std::vector<std::pair<double, double>> iv) {
