@@ -121,6 +121,34 @@ __host__ __device__ inline void key_word_to_table(uint32_t bits, uint32_t kw, Or
     key_word_to_table_at<D, LAY, DUAL>(bits, lds_from_key(kw << 5, D, LAY), or_into);
 }
 
+// d = 4 in the compact order, four key words at once: the key words kw0 +
+// {0, 2, 16, 18} (kw0 with bits 1 and 4 clear) differ only in B'2 and B'3,
+// which are bits 2 and 3 of an LDS bit index, so they come from the same four
+// LDS words (G'1 and R'0 vary: word offsets 0, 1, 8, 9).  Each of those words
+// holds, for key word j (j = B'2 + 2 B'3), the nibble of G'0 = 0 at bit 4j and
+// that of G'0 = 1 at bit 16 + 4j.  DUAL: the occupancy words of a dual table.
+template <bool DUAL = false>
+__host__ __device__ inline void key_quad_from_table_d4(const uint32_t *tab, uint32_t kw0, uint32_t (&out)[4]) {
+    const uint32_t w0 = lds_from_key(kw0 << 5, 4, LAY_COMPACT) >> 5;
+    uint32_t wd[4];   // index G'1 + 2 R'0
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const uint32_t w = w0 + (uint32_t)(m & 1) + 8u * (uint32_t)(m >> 1);
+        wd[m] = tab[DUAL ? 2 * w + 1 : w];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int g0 = 0; g0 < 2; ++g0)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t n = (wd[m] >> (16 * g0 + 4 * j)) & 0xFu;
+                out[j] |= nib_spread(n) << (16 * (m & 1) + 4 * (m >> 1) + 2 * g0);
+            }
+}
+
 // Exact unsigned division by a runtime-invariant divisor with one high
 // multiply (Granlund & Montgomery, PLDI 1994, unsigned case, N = 32).
 struct FastDiv {

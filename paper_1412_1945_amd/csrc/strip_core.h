@@ -119,6 +119,28 @@ __device__ __forceinline__ void occ_from_lds(const uint32_t *lds, uint32_t *__re
         }
         return;
     }
+    if constexpr (D == 4 && PAD == LAY_COMPACT) {
+        // four key words per lane from one read of the four LDS words they
+        // share (the region tables: 128 key words per tile)
+        constexpr int QW = KW / 4;
+        for (int i = tid; i < n_tiles * QW; i += nt) {
+            const int c = i / QW;
+            const uint32_t q = (uint32_t)(i - c * QW);
+            const uint32_t kw0 = (q & 1u) | ((q & 6u) << 1) | ((q & 0x18u) << 2);
+            uint32_t out[4];
+            key_quad_from_table_d4<DUAL>(lds + c * LW, kw0, out);
+            uint32_t *o = occ + (int64_t)c * KW + kw0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int at = 2 * (j & 1) + 16 * (j >> 1);
+                if (store)
+                    o[at] = out[j];
+                else if (out[j])
+                    atomicOr(&o[at], out[j]);
+            }
+        }
+        return;
+    }
     const KeyWordBase<D, PAD> kbase(tid, KW);
     for (int i = tid; i < n_tiles * KW; i += nt) {
         const int c = i / KW;

@@ -65,7 +65,44 @@ static void check_words(uint64_t seed) {
     free(tab2);
 }
 
+// d = 4, compact order: the four-word gather equals the one-word gather for
+// every quad of key words, plain and dual tables.
+static void check_quads(uint64_t seed) {
+    const uint32_t lw = (uint32_t)lds_words(4, LAY_COMPACT);
+    uint32_t tab[128], dt[256];
+    for (int trial = 0; trial < 20; ++trial) {
+        for (uint32_t i = 0; i < lw; ++i) {
+            seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
+            tab[i] = trial % 3 == 0 ? (uint32_t)seed : trial % 3 == 1 ? (uint32_t)seed & (uint32_t)(seed >> 32) : 0u;
+        }
+        for (uint32_t i = 0; i < 2 * lw; ++i) {
+            seed ^= seed << 13; seed ^= seed >> 7; seed ^= seed << 17;
+            dt[i] = (uint32_t)seed;
+        }
+        for (uint32_t q = 0; q < 32; ++q) {
+            const uint32_t kw0 = (q & 1u) | ((q & 6u) << 1) | ((q & 0x18u) << 2);
+            CHECK((kw0 & 0x12u) == 0);
+            uint32_t out[4], outd[4];
+            key_quad_from_table_d4(tab, kw0, out);
+            key_quad_from_table_d4<true>(dt, kw0, outd);
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t kw = kw0 + 2u * (uint32_t)(j & 1) + 16u * (uint32_t)(j >> 1);
+                CHECK(out[j] == (key_word_from_table<4, LAY_COMPACT>(tab, kw)));
+                CHECK(outd[j] == (key_word_from_table<4, LAY_COMPACT, true>(dt, kw)));
+            }
+        }
+    }
+    // the 32 quads cover the 128 key words once each
+    int seen[128] = {0};
+    for (uint32_t q = 0; q < 32; ++q) {
+        const uint32_t kw0 = (q & 1u) | ((q & 6u) << 1) | ((q & 0x18u) << 2);
+        for (int j = 0; j < 4; ++j) ++seen[kw0 + 2 * (j & 1) + 16 * (j >> 1)];
+    }
+    for (int i = 0; i < 128; ++i) CHECK(seen[i] == 1);
+}
+
 int main() {
+    check_quads(12345);
     // the conversion loops' split of lds_from_key(32 kw) into a lane part
     // (tid mod KW) and a part common to a wave's lanes (kw - tid mod KW)
     for (int lay = 0; lay < 2; ++lay)
