@@ -364,6 +364,7 @@ __device__ __forceinline__ void span_loop(const StripArgs &a, __amdgpu_buffer_rs
 // group of frames, Section 3); n_trees is the window length in slots.
 constexpr int kMergeWaves = 4;      // waves of a merge workgroup: 64 words x 4 parts of the window
 constexpr int kMergeBlock = 64 * kMergeWaves;
+constexpr int64_t kMergeWholeWords = 1 << 19;   // merges of at least this many words: one thread per word
 
 // Add into c the trees (or groups) j = j0, j0 + step, ... of the window for
 // word i.  Sixteen loads per round, independent and in flight together.
@@ -415,17 +416,22 @@ __device__ __forceinline__ void merge_count(uint32_t (&c)[16], const uint32_t *_
     }
 }
 
-// Words w0 .. w0+63 of one merge by a workgroup of kMergeBlock threads (the
-// call is workgroup-uniform): wave q counts the window's trees j = q, q + 4,
-// ... for the 64 words, the four partial counts meet in LDS (`part`, 3 x 16 x
-// 64 words) and the first wave adds them bit-sliced, compares with kmin and
-// writes leaf[w0 .. w0+63] (words below `words` only).
+// Words of one merge by a workgroup of kMergeBlock threads (the call is
+// workgroup-uniform).  SPLIT = 4: words w0 .. w0+63; wave q counts the
+// window's trees j = q, q + 4, ... for the 64 words, the four partial counts
+// meet in LDS (`part`, 3 x 16 x 64 words) and the first wave adds them
+// bit-sliced, compares with kmin and writes leaf[w0 .. w0+63] (words below
+// `words` only).  SPLIT = 1: words w0 .. w0+255, one thread per word over the
+// whole window (large merges: enough words to fill the chip without
+// splitting the window, and no partial counts to meet).
+template <int SPLIT = kMergeWaves>
 __device__ __forceinline__ void merge_block(const uint32_t *__restrict__ ring, int ring_len, int first, int n_trees,
                                             int64_t slot_words, int64_t words, int64_t w0, int valid_bits,
                                             uint32_t kmin, int planes, int empty, int group,
                                             uint32_t *__restrict__ leaf, uint32_t *part) {
-    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t i = w0 + lane;
+    static_assert(SPLIT == 1 || SPLIT == kMergeWaves, "a window is counted whole or in four parts");
+    const int lane = threadIdx.x & 63, q = SPLIT == 1 ? 0 : (int)(threadIdx.x >> 6);
+    const int64_t i = w0 + (SPLIT == 1 ? (int64_t)threadIdx.x : (int64_t)lane);
     const uint32_t valid = valid_bits >= 32 ? 0xFFFFFFFFu : ((1u << valid_bits) - 1u);
     if (empty) {
         if (q == 0 && i < words) leaf[i] = 0;
@@ -434,16 +440,18 @@ __device__ __forceinline__ void merge_block(const uint32_t *__restrict__ ring, i
     uint32_t c[16];
 #pragma unroll
     for (int b = 0; b < 16; ++b) c[b] = 0;
-    if (i < words) merge_count(c, ring, ring_len, first, n_trees, slot_words, i, valid, planes, group, q, kMergeWaves);
-    if (q > 0) {
+    if (i < words) merge_count(c, ring, ring_len, first, n_trees, slot_words, i, valid, planes, group, q, SPLIT);
+    if (SPLIT > 1) {
+        if (q > 0) {
 #pragma unroll
-        for (int b = 0; b < 16; ++b)
-            if (b < planes) part[((q - 1) * 16 + b) * 64 + lane] = c[b];
+            for (int b = 0; b < 16; ++b)
+                if (b < planes) part[((q - 1) * 16 + b) * 64 + lane] = c[b];
+        }
+        __syncthreads();
+        if (q != 0) return;
     }
-    __syncthreads();
-    if (q != 0) return;
 #pragma unroll
-    for (int r = 0; r < kMergeWaves - 1; ++r) {
+    for (int r = 0; r < SPLIT - 1; ++r) {
         // c += part r, bit-sliced ripple carry (the sum of all counts fits in
         // `planes` bits: it is at most n_trees)
         uint32_t carry = 0;
