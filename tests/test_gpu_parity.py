@@ -157,6 +157,36 @@ def test_merge_ring_windows(env):
             assert np.array_equal(u32(leaf).reshape(want.shape), want)
 
 
+def test_merge_large_one_thread_per_word(env):
+    """Merges of at least 512 K words (a 4K frame with 32x32 regions: 8160
+    trees of 128 words) count each word's window in one thread instead of
+    four waves; against the oracle on synthetic bitsets, with windows that
+    wrap the ring and groups of two slots (a group's tree holds what any of
+    its slots holds)."""
+    obg, O = env
+    rng = np.random.default_rng(4242)
+    g = obg.FrameGeom(3840, 2160, 4, region_w=32, region_h=32)
+    assert g.n_regions * g.words >= 1 << 19
+    ring = 6
+    bits = rng.random((ring, g.n_regions, 4096)) < 0.05
+    occ = np.packbits(bits, axis=-1, bitorder="little").view(np.uint32).reshape(ring, g.n_regions, g.words)
+    del bits
+    docc = torch.from_numpy(occ.view(np.int32).copy()).cuda()
+    for first, n, grp, num, den in [(4, 5, 1, 1, 2), (0, 6, 1, 1, 3), (3, 5, 2, 1, 2), (5, 6, 2, 2, 3)]:
+        print(f"[case] large merge regions=8160 first={first} n={n} group={grp} thr={num}/{den}", flush=True)
+        leaf = obg.empty_leafset(g)
+        if grp == 1:
+            obg.obg_merge(g, docc, ring, first, n, num, den, leaf)
+        else:
+            obg.obg_merge_groups(g, docc, ring, first, n, grp, num, den, leaf)
+        torch.cuda.synchronize()
+        slots = [occ[(first + t) % ring] for t in range(n)]
+        trees = [np.bitwise_or.reduce(np.stack(slots[i: i + grp]), axis=0) for i in range(0, n, grp)]
+        f = O.Forest(g.width, g.height, 4, 32, 32)
+        want = f.merge([f.add_occupancy(t) for t in trees], num, den).leafset()
+        assert np.array_equal(u32(leaf).reshape(want.shape), want)
+
+
 def test_merge_groups_of_frames(env):
     """Trees of groups of consecutive frames (Section 3): the GPU merge of
     grouped ring windows against the oracle's group trees built from the
