@@ -453,7 +453,8 @@ __device__ __forceinline__ void merge_block(const uint32_t *__restrict__ ring, i
 #pragma unroll
     for (int r = 0; r < SPLIT - 1; ++r) {
         // c += part r, bit-sliced ripple carry (the sum of all counts fits in
-        // `planes` bits: it is at most n_trees)
+        // `planes` bits: it is at most the window's number of trees, or of
+        // groups)
         uint32_t carry = 0;
 #pragma unroll
         for (int b = 0; b < 16; ++b) {
